@@ -1,0 +1,272 @@
+/*
+ * mpr.h -- C ABI of libmpr: exact (min,+) matrix powers on AMD Instinct
+ * MI355X (gfx950) for the Roman domination number of cylinders P_m x C_n,
+ * after Martinez, Garzon and Puertas, "Powers of large matrices on GPU
+ * platforms to compute the Roman domination number of cylindrical graphs"
+ * (arXiv 2409.17658).
+ *
+ * Storage.  Matrices are row-major uint16 with a leading dimension (ld, in
+ * elements, ld >= number of columns).  0xFFFF (MPR_INF) is +infinity, the
+ * absorbing element of the (min,+) semiring of Section 3.  A matrix that
+ * enters a product must have every finite entry <= MPR_FMAX (0x7FFF): the
+ * kernels add with unsigned saturation, so every finite sum is <= 0xFFFE and
+ * can never be mistaken for infinity.
+ *
+ * Canonical form of a power.  A power P = A^k is kept as (N, R): R[i] is the
+ * least finite entry of row i of P (int64), N = P - R row-wise (so every
+ * non-empty row of N has minimum 0).  A row of P with no finite entry has
+ * R[i] = MPR_ROW_NONE and an all-infinite row in N.  By the scalar rule of
+ * Section 3 ((alpha (x) A) (x) B = alpha (x) (A (x) B)) the pair determines P
+ * exactly, and the form is unique.
+ *
+ * Pointers.  Every matrix / vector argument is a DEVICE pointer unless its
+ * name ends in _host.  All buffers are owned by the caller; the library
+ * keeps no pointer after a call returns.  Workspaces are sized with the
+ * matching *_workspace_size call and passed in; the compute entry points
+ * allocate no device memory.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Calls are stream-ordered and asynchronous unless documented as
+ * synchronous.
+ *
+ * Errors.  Argument errors are returned synchronously.  Data-dependent
+ * errors (a finite value above MPR_FMAX that would enter a product) are
+ * reported on the device: *d_status (a device int32 the caller zeroes) is
+ * set to MPR_EOVERFLOW, and the results of that call are then unspecified.
+ * A wrong answer is never produced silently: either *d_status stays 0 or
+ * the call's outputs must be discarded.
+ */
+#ifndef MPR_H
+#define MPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPR_OK = 0,
+    MPR_EINVAL = 1,       /* bad argument (size, pointer, leading dimension) */
+    MPR_ENOMEM = 2,       /* workspace too small */
+    MPR_EOVERFLOW = 3,    /* finite value above MPR_FMAX would enter a product */
+    MPR_ENOTFOUND = 4,    /* no periodic regime up to the requested power */
+    MPR_EHIP = 5,         /* HIP runtime error */
+    MPR_EUNSUPPORTED = 6  /* no gfx950 device, or a size beyond the limits */
+} mpr_status;
+
+#define MPR_INF 0xFFFFu
+#define MPR_FMAX 0x7FFFu
+#define MPR_ROW_NONE INT64_MAX
+#define MPR_CHAIN 0  /* A^e = (((A (x) A) (x) A) ...): e-1 products */
+#define MPR_SQUARE 1 /* binary powering: squares A^(2^j) and their products */
+
+typedef void *mpr_stream;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int mpr_version(void);
+/* Static string naming a status code. */
+const char *mpr_status_string(int status);
+/* Checks that device `device` is a gfx950 part and records its CU count.
+ * Synchronous.  Called implicitly by every entry point on first use. */
+mpr_status mpr_init(int device);
+
+/* ------------------------------------------------------------------ */
+/* Transfer matrix (Section 4.1, Definition 4, Corollary 7).           */
+/* ------------------------------------------------------------------ */
+
+/* Number of correct words of length m (Definition 4; Table 1 lists them):
+ * words over {a,b,c,d} with none of ad, da, ab, ba, bb as neighbours.
+ * 1 <= m <= 12.  Synchronous, host only. */
+mpr_status mpr_transfer_size(int m, int64_t *n_states_host);
+
+/* The correct words in state order (increasing base-4 value, row 1 the most
+ * significant letter; a=0, b=1, c=2, d=3), m bytes per word, into the host
+ * buffer words_host of capacity_words words.  Synchronous, host only. */
+mpr_status mpr_transfer_words(int m, uint8_t *words_host, int64_t capacity_words);
+
+/* Writes A(G) of Corollary 7 into the device matrix A (n x n, n from
+ * mpr_transfer_size, row stride lda >= n): A[q][p] = 2 p(a) + p(b) when
+ * word p can follow word q under the rule lists of Section 4.1 (row q is
+ * the previous column, p the next), else MPR_INF.  1 <= m <= 11. */
+mpr_status mpr_build_transfer(int m, uint16_t *A, int64_t lda, mpr_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* (min,+) products (Section 3).                                       */
+/* ------------------------------------------------------------------ */
+
+/* C = A (x) B: C[i][j] = min_k sat(A[i][k] + B[k][j]) with A M x K (lda),
+ * B K x N (ldb), C M x N (ldc).  Exact for inputs whose finite entries are
+ * <= MPR_FMAX; when d_status != NULL the inputs are checked first and
+ * *d_status is set to MPR_EOVERFLOW if one is not (pass NULL only when the
+ * caller guarantees the bound).  Finite outputs are exact values in
+ * [0, 0xFFFE].  M, N, K >= 0 (an empty K gives an all-MPR_INF C).  C must
+ * not overlap A or B.  Fast path: A, B, C 16-byte aligned and lda, ldb, ldc
+ * multiples of 8; any other layout takes a slower element-wise path. */
+mpr_status mpr_minplus_gemm(int64_t M, int64_t N, int64_t K,
+                            const uint16_t *A, int64_t lda,
+                            const uint16_t *B, int64_t ldb,
+                            uint16_t *C, int64_t ldc,
+                            int32_t *d_status, mpr_stream stream);
+
+/* Same with an explicit tile configuration (0 <= cfg < mpr_gemm_config_count);
+ * used by the autotuner.  cfg = -1 picks from the tile table. */
+mpr_status mpr_minplus_gemm_cfg(int cfg, int64_t M, int64_t N, int64_t K,
+                                const uint16_t *A, int64_t lda,
+                                const uint16_t *B, int64_t ldb,
+                                uint16_t *C, int64_t ldc,
+                                int32_t *d_status, mpr_stream stream);
+
+/* Row-min normalisation in place: for each row i of the M x N matrix C,
+ * r_i = least finite entry, C[i][:] -= r_i (MPR_INF stays), and
+ * R_out[i] = R_in[i] + r_i (R_in may be NULL, read as 0; R_in may equal
+ * R_out).  An all-infinite row, or R_in[i] == MPR_ROW_NONE, gives
+ * R_out[i] = MPR_ROW_NONE.  *d_status = MPR_EOVERFLOW when a normalised
+ * finite entry exceeds MPR_FMAX (the result can not enter a product). */
+mpr_status mpr_normalise(int64_t M, int64_t N, uint16_t *C, int64_t ldc,
+                         const int64_t *R_in, int64_t *R_out,
+                         int32_t *d_status, mpr_stream stream);
+
+/* Workspace bytes for mpr_minplus_gemm_norm with a K x N right operand. */
+mpr_status mpr_gemm_norm_workspace_size(int64_t K, int64_t N, size_t *bytes_host);
+
+/* Canonical product of two canonical forms:
+ * (Rc, C) = canon((Ra (+) A) (x) (Rb (+) B)).  With s = min_l Rb[l], the
+ * right operand is folded to B'[l][j] = B[l][j] + (Rb[l] - s) (scalar rule
+ * of Section 3) in the workspace, then C = canon(A (x) B') and
+ * Rc = Ra + s + rowmin.  Ra / Rb may be NULL (all zero).  A is M x K, B is
+ * K x N, C is M x N.  *d_status = MPR_EOVERFLOW when a folded entry or a
+ * normalised output exceeds MPR_FMAX. */
+mpr_status mpr_minplus_gemm_norm(int64_t M, int64_t N, int64_t K,
+                                 const uint16_t *A, int64_t lda, const int64_t *Ra,
+                                 const uint16_t *B, int64_t ldb, const int64_t *Rb,
+                                 uint16_t *C, int64_t ldc, int64_t *Rc,
+                                 void *ws, size_t ws_bytes,
+                                 int32_t *d_status, mpr_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Powers (Algorithm 1, step 3; Algorithm 2, step 3).                  */
+/* ------------------------------------------------------------------ */
+
+/* Workspace bytes for mpr_minplus_power on an n x n matrix. */
+mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *bytes_host);
+
+/* Canonical form (N_out, R_out) of A^e for the n x n matrix A, e >= 1.
+ * schedule = MPR_CHAIN computes A^k = A^(k-1) (x) A with A kept raw and a
+ * normalisation after every product (e-1 products); MPR_SQUARE uses binary
+ * powering on canonical forms.  Both give identical bits.  N_out is n x n
+ * (ldo), R_out has n entries. */
+mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t lda, int64_t e,
+                             int schedule, uint16_t *N_out, int64_t ldo, int64_t *R_out,
+                             void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
+
+/* Corollary 7: *d_gamma = min_i (R[i] + N[i][i]) over rows with a finite
+ * diagonal entry (MPR_ROW_NONE if there is none).  For N, R = A^n this is
+ * gamma_R(P_m x C_n), n >= 3. */
+mpr_status mpr_trace_min(const uint16_t *N, int64_t n, int64_t ld, const int64_t *R,
+                         int64_t *d_gamma, mpr_stream stream);
+
+/* Trace of a product without forming it:
+ * *d_gamma = min_i min_l (RX[i] + X[i][l] + RY[l] + Y[l][i]), i.e. the
+ * trace of (RX (+) X) (x) (RY (+) Y).  RX / RY may be NULL (zero). */
+mpr_status mpr_trace_of_product(const uint16_t *X, const int64_t *RX,
+                                const uint16_t *Y, const int64_t *RY,
+                                int64_t n, int64_t ld, int64_t *d_gamma, mpr_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Periodic regime (Lemma 2, Proposition 8, Algorithm 2).              */
+/* ------------------------------------------------------------------ */
+
+/* Workspace bytes to keep `slots` powers of an n x n matrix resident
+ * (slots >= 2; the search can confirm a period mu + lam only when
+ * mu + lam < slots). */
+mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_host);
+
+/* Least (mu, lam, c) with A^(mu+lam) = c (x) A^mu, searching the chain
+ * A^1 .. A^kmax.  The classes of A^k up to a scalar shift form an
+ * eventually periodic sequence; the first repeated class (found by a
+ * 64-bit class hash, then confirmed by an exact compare of (N, R - R'))
+ * gives the least pre-period mu and the least period lam.  When traces_host
+ * is not NULL it receives kmax + 1 int64 values, traces_host[k] = trace of
+ * A^k for k = 1..kmax (the chain then always runs to kmax), else the search
+ * stops at the first confirmed repeat.  SYNCHRONOUS on `stream`.  Returns
+ * MPR_ENOTFOUND when no repeat is confirmed, MPR_EOVERFLOW on overflow. */
+mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax,
+                           int64_t *mu_host, int64_t *lam_host, int64_t *c_host,
+                           int64_t *traces_host, void *ws, size_t ws_bytes, mpr_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Batched power chains: one persistent launch.                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const uint16_t *A; /* device, n x n, row stride lda; finite entries <= MPR_FMAX */
+    int64_t n;
+    int64_t lda;
+    int64_t e;         /* exponent >= 1; computed by the chain schedule */
+    uint16_t *N_out;   /* device, n x n, row stride ldo */
+    int64_t ldo;
+    int64_t *R_out;    /* device, n entries */
+} mpr_chain_desc;
+
+/* Workspace bytes for a batch described by the HOST array descs_host. */
+mpr_status mpr_batch_workspace_size(const mpr_chain_desc *descs_host, int count, size_t *bytes_host);
+
+/* Plans a batch into the workspace: splits every chain into row panels
+ * (row i of A^k depends only on row i of A^(k-1) and on A, so panels never
+ * wait on each other), orders the panels longest first and uploads the
+ * work list.  Synchronous.  The workspace then holds the whole launch
+ * state; mpr_batch_launch may be called (or captured) any number of times. */
+mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count,
+                          void *ws, size_t ws_bytes, mpr_stream stream);
+
+/* Runs a planned batch: resets the work counter with a fill kernel and
+ * launches the persistent kernel (no memset node, no host sync, so the pair
+ * can be captured into a HIP graph).  Results land in each N_out / R_out. */
+mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream stream);
+
+/* Plan + launch. */
+mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count,
+                           void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
+
+/* Number of compiled batched-kernel configurations (panel heights). */
+int mpr_batch_config_count(void);
+/* Rows per panel and threads per workgroup of batched configuration cfg. */
+mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads);
+/* Forces the configuration later mpr_batch_plan calls use (-1 = choose by
+ * a longest-first schedule model of the batch).  Process-wide setting. */
+mpr_status mpr_set_batch_config(int cfg);
+
+/* Captures mpr_batch_launch(ws, d_status) on `stream` into an instantiated
+ * HIP graph returned in *graph_host (opaque).  Synchronous. */
+mpr_status mpr_batch_graph_create(void *ws, int32_t *d_status, mpr_stream stream, void **graph_host);
+/* Replays a captured graph on `stream`. */
+mpr_status mpr_graph_launch(void *graph, mpr_stream stream);
+/* Destroys a captured graph. */
+mpr_status mpr_graph_destroy(void *graph);
+
+/* ------------------------------------------------------------------ */
+/* Tile configurations and the autotuner's table.                      */
+/* ------------------------------------------------------------------ */
+
+/* Number of compiled (min,+) tile configurations. */
+int mpr_gemm_config_count(void);
+/* Describes configuration cfg: tile rows, columns, k depth, per-lane
+ * rows/columns and threads per workgroup (host ints, any may be NULL). */
+mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads);
+/* Installs the size -> configuration table used when cfg = -1: entry t
+ * applies to problems whose largest dimension is <= max_dim_host[t]
+ * (ascending); larger problems use the last entry.  Copies the arrays. */
+mpr_status mpr_set_tile_table(const int64_t *max_dim_host, const int *cfg_host, int entries);
+/* Times every configuration on an n x n x n product (random operands made
+ * inside; allocates, so not for use on a hot path) and writes the average
+ * milliseconds per product into ms_host[cfg]; returns the fastest in
+ * *best_host.  Synchronous. */
+mpr_status mpr_autotune_gemm(int64_t n, int reps, float *ms_host, int *best_host, mpr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPR_H */

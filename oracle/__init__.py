@@ -15,6 +15,8 @@ Functions and the passages they follow:
   transfer(m)                 rule lists of Section 4.1 + the labelling of
                               Corollary 7 (arc q->p weighs 2 p(a) + p(b))
   minplus(X, Y)               the (min,+) product of Section 3
+  minplus_at(X, Y, ii, jj)    single entries of the same product
+  transfer_rows(m, rows)      rows of A(G) alone
   normalise(C)                canonical (N, R) form: row minima pulled out
                               with the scalar rule of Section 3
   product_of_powers(...)      same rule applied to both operands
@@ -75,10 +77,21 @@ def lib():
         L.oracle_trace.argtypes = [i64, p, p]
         L.oracle_brute_gamma.restype = i64
         L.oracle_brute_gamma.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.oracle_minplus_at.restype = None
+        L.oracle_minplus_at.argtypes = [i64, i64, p, p, p, p, i64, p]
+        L.oracle_transfer_rows.restype = ctypes.c_int
+        L.oracle_transfer_rows.argtypes = [ctypes.c_int, p, i64, p]
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_threads.argtypes = []
         L.oracle_rowdp_gamma.restype = i64
         L.oracle_rowdp_gamma.argtypes = [ctypes.c_int, ctypes.c_int]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(lib().oracle_threads())
 
 
 def _ptr(a: np.ndarray):
@@ -150,6 +163,25 @@ def minplus(X, Y) -> np.ndarray:
     if lib().oracle_minplus(M, K, N, _ptr(X), _ptr(Y), _ptr(C)) != 0:
         raise MemoryError("oracle_minplus failed")
     return C
+
+
+def minplus_at(X, Y, ii, jj) -> np.ndarray:
+    """Entries (ii[t], jj[t]) of X (x) Y, each from the definition alone."""
+    X, Y = _c64(X), _c64(Y)
+    ii, jj = _c64(ii), _c64(jj)
+    out = np.empty(len(ii), dtype=np.int64)
+    lib().oracle_minplus_at(X.shape[1], Y.shape[1], _ptr(X), _ptr(Y), _ptr(ii), _ptr(jj), len(ii), _ptr(out))
+    return out
+
+
+def transfer_rows(m: int, rows) -> np.ndarray:
+    """Rows `rows` of A(G) without building the whole matrix."""
+    rows = _c64(rows)
+    n = len(words(m))
+    out = np.empty((len(rows), n), dtype=np.int64)
+    if lib().oracle_transfer_rows(m, _ptr(rows), len(rows), _ptr(out)) != 0:
+        raise RuntimeError("oracle_transfer_rows failed")
+    return out
 
 
 def normalise(C):

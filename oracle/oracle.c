@@ -363,3 +363,56 @@ int64_t oracle_rowdp_gamma(int m, int n)
     free(two); free(zero); free(self); free(wt); free(cur); free(nxt);
     return best;
 }
+
+/* ------------------------------------------------------------------ */
+/* Entry-wise forms for parity checks at sizes where a whole product   */
+/* is too slow for the host.                                           */
+/* ------------------------------------------------------------------ */
+
+/* out[t] = (X (x) Y)[i[t]][j[t]] = min_k X[i][k] + Y[k][j] (finite k only).
+ * X is rows x K (row stride K), Y is K x N (row stride N). */
+void oracle_minplus_at(int64_t K, int64_t N, const int64_t *X, const int64_t *Y,
+                       const int64_t *ii, const int64_t *jj, int64_t count, int64_t *out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < count; t++) {
+        int64_t best = ORACLE_INF;
+        for (int64_t k = 0; k < K; k++) {
+            int64_t x = X[ii[t] * K + k], y = Y[k * N + jj[t]];
+            if (x == ORACLE_INF || y == ORACLE_INF) continue;
+            if (x + y < best) best = x + y;
+        }
+        out[t] = best;
+    }
+}
+
+/* Rows rows[0..count-1] of A(G) (Corollary 7), count x C_m values. */
+int oracle_transfer_rows(int m, const int64_t *rows, int64_t count, int64_t *out)
+{
+    int64_t n = oracle_words(m, NULL);
+    if (n < 0) return -1;
+    uint8_t *w = (uint8_t *)malloc((size_t)(n * m));
+    if (!w) return -2;
+    oracle_words(m, w);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < count; t++)
+        for (int64_t pi = 0; pi < n; pi++) {
+            const uint8_t *q = w + rows[t] * m, *p = w + pi * m;
+            out[t * n + pi] = oracle_follows(q, p, m) ? column_weight(p, m) : ORACLE_INF;
+        }
+    free(w);
+    return 0;
+}
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Threads the OpenMP loops above use (1 without OpenMP). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

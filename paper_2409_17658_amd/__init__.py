@@ -1,0 +1,401 @@
+"""Python binding of libmpr, the MI355X (gfx950) library of exact (min,+)
+matrix powers for the Roman domination number of cylinders P_m x C_n
+(Martinez, Garzon, Puertas, arXiv 2409.17658).
+
+Argument marshalling only: every function here calls the C ABI declared in
+include/mpr.h with device pointers taken from torch tensors; all arithmetic
+runs in the HIP kernels of libmpr.so.  torch supplies device memory and
+streams.  There is no CPU fallback: if libmpr.so has not been built, or no
+gfx950 device is present, the calls raise.
+
+Matrices are 2-D torch.uint16 CUDA tensors with unit column stride; the row
+stride (tensor.stride(0)) is the leading dimension.  alloc_matrix() returns
+a view of a buffer padded to a multiple of 8 columns (the kernels' fast
+path).  Offsets R are int64 CUDA tensors.  0xFFFF is infinity.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpr.so")
+
+INF = 0xFFFF
+FMAX = 0x7FFF
+ROW_NONE = (1 << 63) - 1
+CHAIN = 0
+SQUARE = 1
+
+_STATUS = {0: "MPR_OK", 1: "MPR_EINVAL", 2: "MPR_ENOMEM", 3: "MPR_EOVERFLOW",
+           4: "MPR_ENOTFOUND", 5: "MPR_EHIP", 6: "MPR_EUNSUPPORTED"}
+
+
+class MprError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, _STATUS.get(status, "?"), status))
+
+
+class ChainDesc(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("e", ctypes.c_int64), ("N_out", ctypes.c_void_p), ("ldo", ctypes.c_int64),
+                ("R_out", ctypes.c_void_p)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_SZ = ctypes.c_size_t
+
+_SIGS = {
+    "mpr_version": (_I, []),
+    "mpr_status_string": (ctypes.c_char_p, [_I]),
+    "mpr_init": (_I, [_I]),
+    "mpr_transfer_size": (_I, [_I, _P]),
+    "mpr_transfer_words": (_I, [_I, _P, _I64]),
+    "mpr_build_transfer": (_I, [_I, _P, _I64, _P]),
+    "mpr_minplus_gemm": (_I, [_I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
+    "mpr_minplus_gemm_cfg": (_I, [_I, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
+    "mpr_normalise": (_I, [_I64, _I64, _P, _I64, _P, _P, _P, _P]),
+    "mpr_gemm_norm_workspace_size": (_I, [_I64, _I64, _P]),
+    "mpr_minplus_gemm_norm": (_I, [_I64, _I64, _I64, _P, _I64, _P, _P, _I64, _P, _P, _I64, _P,
+                                   _P, _SZ, _P, _P]),
+    "mpr_power_workspace_size": (_I, [_I64, _I64, _I, _P]),
+    "mpr_minplus_power": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _SZ, _P, _P]),
+    "mpr_trace_min": (_I, [_P, _I64, _I64, _P, _P, _P]),
+    "mpr_trace_of_product": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
+    "mpr_period_workspace_size": (_I, [_I64, _I64, _P]),
+    "mpr_find_period": (_I, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mpr_batch_workspace_size": (_I, [_P, _I, _P]),
+    "mpr_batch_plan": (_I, [_P, _I, _P, _SZ, _P]),
+    "mpr_batch_launch": (_I, [_P, _P, _P]),
+    "mpr_batch_power": (_I, [_P, _I, _P, _SZ, _P, _P]),
+    "mpr_batch_config_count": (_I, []),
+    "mpr_batch_config_info": (_I, [_I, _P, _P]),
+    "mpr_set_batch_config": (_I, [_I]),
+    "mpr_batch_graph_create": (_I, [_P, _P, _P, _P]),
+    "mpr_graph_launch": (_I, [_P, _P]),
+    "mpr_graph_destroy": (_I, [_P]),
+    "mpr_gemm_config_count": (_I, []),
+    "mpr_gemm_config_info": (_I, [_I, _P, _P, _P, _P, _P, _P]),
+    "mpr_set_tile_table": (_I, [_P, _P, _I]),
+    "mpr_autotune_gemm": (_I, [_I64, _I, _P, _P, _P]),
+}
+
+
+def lib():
+    """The loaded libmpr.so (ctypes), with every C-ABI signature declared."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmpr.so is not built (run paper_2409_17658_amd.build.build()); "
+                               "there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _ok(status: int, where: str):
+    if status != 0:
+        raise MprError(status, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA (HIP) tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ld(t):
+    if t.dim() != 2 or t.stride(1) != 1 or t.dtype != torch.uint16:
+        raise ValueError("expected a 2-D uint16 tensor with unit column stride")
+    return max(t.stride(0), t.shape[1], 1)
+
+
+def _status_tensor(device):
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check_status(d_status):
+    """Raise MprError if a device status word is non-zero (synchronises)."""
+    v = int(d_status.item())
+    if v != 0:
+        raise MprError(v, "device status")
+
+
+def round_up(x: int, a: int = 8) -> int:
+    return (x + a - 1) // a * a
+
+
+def alloc_matrix(rows: int, cols: int, device="cuda", fill=None):
+    """rows x cols uint16 view of a buffer whose row stride is a multiple of 8."""
+    buf = torch.empty((rows, round_up(max(cols, 1))), dtype=torch.uint16, device=device)
+    if fill is not None:
+        buf.view(torch.int16).fill_(np.int16(np.uint16(fill).view(np.int16)).item())
+    return buf[:, :cols]
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    """Host uint16 matrix -> padded device view (same values)."""
+    a = np.ascontiguousarray(a, dtype=np.uint16)
+    out = alloc_matrix(a.shape[0], a.shape[1], device)
+    out.copy_(torch.from_numpy(a).to(device))
+    return out
+
+
+def to_host(t) -> np.ndarray:
+    return t.cpu().numpy()
+
+
+def workspace(nbytes: int, device="cuda"):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- info
+def version() -> int:
+    return lib().mpr_version()
+
+
+def init(device: int = 0):
+    _ok(lib().mpr_init(device), "mpr_init")
+
+
+def transfer_size(m: int) -> int:
+    n = ctypes.c_int64()
+    _ok(lib().mpr_transfer_size(m, ctypes.byref(n)), "mpr_transfer_size")
+    return n.value
+
+
+def transfer_words(m: int) -> np.ndarray:
+    n = transfer_size(m)
+    out = np.zeros((n, m), dtype=np.uint8)
+    _ok(lib().mpr_transfer_words(m, out.ctypes.data_as(_P), n), "mpr_transfer_words")
+    return out
+
+
+# ---------------------------------------------------------------- kernels
+def build_transfer(m: int, out=None, stream=None):
+    n = transfer_size(m)
+    A = alloc_matrix(n, n) if out is None else out
+    _ok(lib().mpr_build_transfer(m, _ptr(A), _ld(A), _stream(stream)), "mpr_build_transfer")
+    return A
+
+
+def minplus_gemm(A, B, C=None, check=True, cfg=-1, stream=None, d_status=None):
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = alloc_matrix(M, N, A.device)
+    st = d_status if d_status is not None else (_status_tensor(A.device) if check else None)
+    _ok(lib().mpr_minplus_gemm_cfg(cfg, M, N, K, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C),
+                                   _ptr(st), _stream(stream)), "mpr_minplus_gemm")
+    if check and d_status is None:
+        check_status(st)
+    return C
+
+
+def normalise(C, R_in=None, R_out=None, check=True, stream=None):
+    M, N = C.shape
+    if R_out is None:
+        R_out = torch.empty(M, dtype=torch.int64, device=C.device)
+    st = _status_tensor(C.device) if check else None
+    _ok(lib().mpr_normalise(M, N, _ptr(C), _ld(C), _ptr(R_in), _ptr(R_out), _ptr(st), _stream(stream)),
+        "mpr_normalise")
+    if check:
+        check_status(st)
+    return R_out
+
+
+def minplus_gemm_norm(A, B, Ra=None, Rb=None, C=None, Rc=None, ws=None, check=True, stream=None):
+    M, K = A.shape
+    _, N = B.shape
+    if C is None:
+        C = alloc_matrix(M, N, A.device)
+    if Rc is None:
+        Rc = torch.empty(M, dtype=torch.int64, device=A.device)
+    if ws is None:
+        nb = ctypes.c_size_t()
+        _ok(lib().mpr_gemm_norm_workspace_size(K, N, ctypes.byref(nb)), "mpr_gemm_norm_workspace_size")
+        ws = workspace(nb.value, A.device)
+    st = _status_tensor(A.device) if check else None
+    _ok(lib().mpr_minplus_gemm_norm(M, N, K, _ptr(A), _ld(A), _ptr(Ra), _ptr(B), _ld(B), _ptr(Rb), _ptr(C),
+                                    _ld(C), _ptr(Rc), _ptr(ws), ws.numel(), _ptr(st), _stream(stream)),
+        "mpr_minplus_gemm_norm")
+    if check:
+        check_status(st)
+    return C, Rc
+
+
+def power_workspace_size(n: int, e: int, schedule: int = CHAIN) -> int:
+    nb = ctypes.c_size_t()
+    _ok(lib().mpr_power_workspace_size(n, e, schedule, ctypes.byref(nb)), "mpr_power_workspace_size")
+    return nb.value
+
+
+def minplus_power(A, e: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=None, check=True, stream=None,
+                  d_status=None):
+    n = A.shape[0]
+    if N_out is None:
+        N_out = alloc_matrix(n, n, A.device)
+    if R_out is None:
+        R_out = torch.empty(n, dtype=torch.int64, device=A.device)
+    if ws is None:
+        ws = workspace(power_workspace_size(n, e, schedule), A.device)
+    st = d_status if d_status is not None else (_status_tensor(A.device) if check else None)
+    _ok(lib().mpr_minplus_power(_ptr(A), n, _ld(A), e, schedule, _ptr(N_out), _ld(N_out), _ptr(R_out),
+                                _ptr(ws), ws.numel(), _ptr(st), _stream(stream)), "mpr_minplus_power")
+    if check and d_status is None:
+        check_status(st)
+    return N_out, R_out
+
+
+def trace_min(N, R, out=None, stream=None):
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=N.device)
+    _ok(lib().mpr_trace_min(_ptr(N), N.shape[0], _ld(N), _ptr(R), _ptr(out), _stream(stream)), "mpr_trace_min")
+    return out
+
+
+def trace_of_product(X, RX, Y, RY, out=None, stream=None):
+    if X.stride(0) != Y.stride(0):
+        raise ValueError("X and Y must share a leading dimension")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=X.device)
+    _ok(lib().mpr_trace_of_product(_ptr(X), _ptr(RX), _ptr(Y), _ptr(RY), X.shape[0], _ld(X), _ptr(out),
+                                   _stream(stream)), "mpr_trace_of_product")
+    return out
+
+
+def period_workspace_size(n: int, slots: int) -> int:
+    nb = ctypes.c_size_t()
+    _ok(lib().mpr_period_workspace_size(n, slots, ctypes.byref(nb)), "mpr_period_workspace_size")
+    return nb.value
+
+
+def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None):
+    """(mu, lam, c, traces) with traces[k] = trace of A^k for k = 1..kmax
+    (None when traces=False); mu is None when no period is confirmed."""
+    n = A.shape[0]
+    if ws is None:
+        ws = workspace(period_workspace_size(n, slots), A.device)
+    mu, lam, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    tr = np.zeros(kmax + 1, dtype=np.int64) if traces else None
+    st = lib().mpr_find_period(_ptr(A), n, _ld(A), kmax, ctypes.byref(mu), ctypes.byref(lam), ctypes.byref(c),
+                               tr.ctypes.data_as(_P) if traces else None, _ptr(ws), ws.numel(), _stream(stream))
+    if st == 4:
+        return None, None, None, tr
+    _ok(st, "mpr_find_period")
+    return mu.value, lam.value, c.value, tr
+
+
+# ---------------------------------------------------------------- batched chains
+def _descs(chains):
+    arr = (ChainDesc * len(chains))()
+    for i, (A, e, N_out, R_out) in enumerate(chains):
+        arr[i] = ChainDesc(A.data_ptr(), A.shape[0], _ld(A), int(e), N_out.data_ptr(), _ld(N_out), R_out.data_ptr())
+    return arr
+
+
+def batch_workspace_size(chains) -> int:
+    d = _descs(chains)
+    nb = ctypes.c_size_t()
+    _ok(lib().mpr_batch_workspace_size(d, len(chains), ctypes.byref(nb)), "mpr_batch_workspace_size")
+    return nb.value
+
+
+def batch_plan(chains, ws, stream=None):
+    """chains: list of (A, e, N_out, R_out) device tensors."""
+    d = _descs(chains)
+    _ok(lib().mpr_batch_plan(d, len(chains), _ptr(ws), ws.numel(), _stream(stream)), "mpr_batch_plan")
+
+
+def batch_launch(ws, d_status=None, stream=None):
+    _ok(lib().mpr_batch_launch(_ptr(ws), _ptr(d_status), _stream(stream)), "mpr_batch_launch")
+
+
+def batch_power(chains, ws=None, check=True, stream=None):
+    if ws is None:
+        ws = workspace(batch_workspace_size(chains), chains[0][0].device)
+    st = _status_tensor(chains[0][0].device) if check else None
+    batch_plan(chains, ws, stream)
+    batch_launch(ws, st, stream)
+    if check:
+        check_status(st)
+    return ws
+
+
+def batch_graph_create(ws, d_status=None, stream=None):
+    g = ctypes.c_void_p()
+    _ok(lib().mpr_batch_graph_create(_ptr(ws), _ptr(d_status), _stream(stream), ctypes.byref(g)),
+        "mpr_batch_graph_create")
+    return g
+
+
+def graph_launch(graph, stream=None):
+    _ok(lib().mpr_graph_launch(graph, _stream(stream)), "mpr_graph_launch")
+
+
+def graph_destroy(graph):
+    _ok(lib().mpr_graph_destroy(graph), "mpr_graph_destroy")
+
+
+def batch_config_count() -> int:
+    return lib().mpr_batch_config_count()
+
+
+def batch_config_info(cfg: int):
+    r, t = ctypes.c_int(), ctypes.c_int()
+    _ok(lib().mpr_batch_config_info(cfg, ctypes.byref(r), ctypes.byref(t)), "mpr_batch_config_info")
+    return {"panel_rows": r.value, "threads": t.value}
+
+
+def set_batch_config(cfg: int):
+    _ok(lib().mpr_set_batch_config(cfg), "mpr_set_batch_config")
+
+
+# ---------------------------------------------------------------- tiles / tuning
+def gemm_config_count() -> int:
+    return lib().mpr_gemm_config_count()
+
+
+def gemm_config_info(cfg: int):
+    v = [ctypes.c_int() for _ in range(6)]
+    _ok(lib().mpr_gemm_config_info(cfg, *[ctypes.byref(x) for x in v]), "mpr_gemm_config_info")
+    return dict(zip(["bm", "bn", "bk", "tm", "tn", "threads"], [x.value for x in v]))
+
+
+def set_tile_table(table):
+    """table: list of (max_dim, cfg), ascending max_dim."""
+    md = (ctypes.c_int64 * len(table))(*[int(a) for a, _ in table])
+    cf = (ctypes.c_int * len(table))(*[int(b) for _, b in table])
+    _ok(lib().mpr_set_tile_table(md, cf, len(table)), "mpr_set_tile_table")
+
+
+def autotune_gemm(n: int, reps: int = 3, stream=None):
+    cnt = gemm_config_count()
+    ms = (ctypes.c_float * cnt)()
+    best = ctypes.c_int()
+    _ok(lib().mpr_autotune_gemm(n, reps, ms, ctypes.byref(best), _stream(stream)), "mpr_autotune_gemm")
+    return best.value, list(ms)

@@ -1,0 +1,476 @@
+// abi.hip -- the extern "C" entry points of libmpr: argument checks, device
+// set-up, workspace layouts, and the host-side schedules built from the
+// kernels (chain and binary powering, products of canonical forms, the
+// period search of Algorithm 2).
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace mpr {
+
+mpr_status transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s);
+int64_t transfer_size(int m);
+void transfer_words(int m, uint8_t *out, int64_t count);
+
+hipStream_t as_stream(mpr_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+mpr_status check_launch()
+{
+    return hipGetLastError() == hipSuccess ? MPR_OK : MPR_EHIP;
+}
+
+static std::mutex g_init_mu;
+static std::vector<int> g_cus;  // per device: CU count, 0 = not gfx950, -1 = unknown
+
+static mpr_status init_device(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if ((int)g_cus.size() <= dev) g_cus.resize(dev + 1, -1);
+    if (g_cus[dev] > 0) return MPR_OK;
+    if (g_cus[dev] == 0) return MPR_EUNSUPPORTED;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MPR_EHIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_cus[dev] = 0;
+        return MPR_EUNSUPPORTED;
+    }
+    g_cus[dev] = prop.multiProcessorCount;
+    return MPR_OK;
+}
+
+mpr_status ensure_init()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MPR_EUNSUPPORTED;
+    return init_device(dev);
+}
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    return (dev < (int)g_cus.size() && g_cus[dev] > 0) ? g_cus[dev] : 256;
+}
+
+// ------------------------------------------------------------ workspace carving
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <class X>
+    X *take(size_t count)
+    {
+        used = (size_t)round_up((int64_t)used, 256);
+        X *p = base ? (X *)(base + used) : nullptr;
+        used += count * sizeof(X);
+        return p;
+    }
+};
+
+static bool ld_ok(int64_t ld, int64_t cols) { return ld >= (cols > 0 ? cols : 1); }
+
+// Canonical product (Rc, C) = canon((Ra (+) A) (x) (Rb (+) B)) on carved scratch.
+static mpr_status gemm_norm_impl(int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const int64_t *Ra,
+                                 const u16 *B, int64_t ldb, const int64_t *Rb, u16 *C, int64_t ldc, int64_t *Rc,
+                                 int64_t *s_scalar, u16 *Bp, int64_t ldp, int32_t *st, hipStream_t s)
+{
+    mpr_status e;
+    if (Rb) {
+        e = fold_launch(B, ldb, Rb, K, N, Bp, ldp, s_scalar, st, s);
+        if (e != MPR_OK) return e;
+        B = Bp;
+        ldb = ldp;
+    }
+    e = gemm_launch(-1, M, N, K, A, lda, B, ldb, C, ldc, s);
+    if (e != MPR_OK) return e;
+    return normalise_launch(M, N, C, ldc, Ra, Rb ? s_scalar : nullptr, Rc, st, nullptr, s);
+}
+
+static size_t gemm_norm_ws(int64_t K, int64_t N, int64_t *ldp_out)
+{
+    const int64_t ldp = round_up(N > 0 ? N : 1, 8);
+    Carver c(nullptr);
+    c.take<int64_t>(1);
+    c.take<u16>((size_t)(K * ldp));
+    if (ldp_out) *ldp_out = ldp;
+    return c.used + 256;
+}
+
+// ------------------------------------------------------------ powers
+struct PowerWs {
+    u16 *P, *acc, *Bp, *C;
+    int64_t *RP, *Racc, *RC, *s;
+    int64_t ld;
+    size_t bytes;
+};
+
+static PowerWs carve_power(void *ws, int64_t n, int schedule)
+{
+    PowerWs w{};
+    w.ld = round_up(n > 0 ? n : 1, 8);
+    Carver c(ws);
+    w.P = c.take<u16>((size_t)(n * w.ld));
+    if (schedule == MPR_SQUARE) {
+        w.acc = c.take<u16>((size_t)(n * w.ld));
+        w.Bp = c.take<u16>((size_t)(n * w.ld));
+        w.C = c.take<u16>((size_t)(n * w.ld));
+        w.RP = c.take<int64_t>((size_t)n);
+        w.Racc = c.take<int64_t>((size_t)n);
+        w.RC = c.take<int64_t>((size_t)n);
+        w.s = c.take<int64_t>(1);
+    }
+    w.bytes = c.used + 256;
+    return w;
+}
+
+static mpr_status power_chain(const u16 *A, int64_t n, int64_t lda, int64_t e, u16 *N_out, int64_t ldo,
+                              int64_t *R_out, const PowerWs &w, int32_t *st, hipStream_t s)
+{
+    // Step k writes buffer (e - k) % 2, so step e lands in N_out.
+    u16 *buf[2] = {N_out, w.P};
+    const int64_t ld[2] = {ldo, w.ld};
+    int b = (int)((e - 1) & 1);
+    mpr_status r = copy_launch(A, lda, buf[b], ld[b], n, n, s);
+    if (r == MPR_OK) r = normalise_launch(n, n, buf[b], ld[b], nullptr, nullptr, R_out, st, nullptr, s);
+    for (int64_t k = 2; k <= e && r == MPR_OK; k++) {
+        const int nb = b ^ 1;
+        r = gemm_launch(-1, n, n, n, buf[b], ld[b], A, lda, buf[nb], ld[nb], s);
+        if (r == MPR_OK) r = normalise_launch(n, n, buf[nb], ld[nb], R_out, nullptr, R_out, st, nullptr, s);
+        b = nb;
+    }
+    return r;
+}
+
+static mpr_status power_square(const u16 *A, int64_t n, int64_t lda, int64_t e, u16 *N_out, int64_t ldo,
+                               int64_t *R_out, const PowerWs &w, int32_t *st, hipStream_t s)
+{
+    u16 *P = w.P, *acc = w.acc, *C = w.C;
+    int64_t *RP = w.RP, *Racc = w.Racc, *RC = w.RC;
+    const int64_t ld = w.ld;
+    mpr_status r = copy_launch(A, lda, P, ld, n, n, s);
+    if (r == MPR_OK) r = normalise_launch(n, n, P, ld, nullptr, nullptr, RP, st, nullptr, s);
+    bool have = false;
+    while (r == MPR_OK) {
+        if (e & 1) {
+            if (!have) {
+                r = copy_launch(P, ld, acc, ld, n, n, s);
+                if (r == MPR_OK && hipMemcpyAsync(Racc, RP, (size_t)n * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    r = MPR_EHIP;
+                have = true;
+            } else {
+                r = gemm_norm_impl(n, n, n, acc, ld, Racc, P, ld, RP, C, ld, RC, w.s, w.Bp, ld, st, s);
+                std::swap(acc, C);
+                std::swap(Racc, RC);
+            }
+        }
+        e >>= 1;
+        if (!e || r != MPR_OK) break;
+        r = gemm_norm_impl(n, n, n, P, ld, RP, P, ld, RP, C, ld, RC, w.s, w.Bp, ld, st, s);
+        std::swap(P, C);
+        std::swap(RP, RC);
+    }
+    if (r == MPR_OK) r = copy_launch(acc, ld, N_out, ldo, n, n, s);
+    if (r == MPR_OK && hipMemcpyAsync(R_out, Racc, (size_t)n * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        r = MPR_EHIP;
+    return r;
+}
+
+// ------------------------------------------------------------ period search
+struct PeriodWs {
+    uint64_t *row_hash;
+    int64_t *scal;  // [0] hash, [1] trace, [2] status (int32 in low half), [3..5] compare
+    int64_t slots;
+    int64_t ld;
+    size_t slot_elems;  // u16 per slot (matrix) + R follows after padding
+    char *slot_base;
+    size_t slot_bytes;
+    size_t fixed;
+};
+
+static PeriodWs carve_period(void *ws, int64_t n, size_t ws_bytes, int64_t slots_req)
+{
+    PeriodWs w{};
+    w.ld = round_up(n > 0 ? n : 1, 8);
+    Carver c(ws);
+    w.row_hash = c.take<uint64_t>((size_t)n);
+    w.scal = c.take<int64_t>(8);
+    w.fixed = (size_t)round_up((int64_t)c.used, 256);
+    w.slot_elems = (size_t)(n * w.ld);
+    w.slot_bytes = (size_t)round_up((int64_t)(w.slot_elems * 2), 256) + (size_t)round_up(n * 8, 256);
+    w.slot_base = ws ? (char *)ws + w.fixed : nullptr;
+    if (slots_req > 0)
+        w.slots = slots_req;
+    else
+        w.slots = ws_bytes > w.fixed ? (int64_t)((ws_bytes - w.fixed) / w.slot_bytes) : 0;
+    return w;
+}
+
+static inline u16 *slot_N(const PeriodWs &w, int64_t k) { return (u16 *)(w.slot_base + (size_t)k * w.slot_bytes); }
+static inline int64_t *slot_R(const PeriodWs &w, int64_t k)
+{
+    return (int64_t *)(w.slot_base + (size_t)k * w.slot_bytes + (size_t)round_up((int64_t)(w.slot_elems * 2), 256));
+}
+
+}  // namespace mpr
+
+using namespace mpr;
+
+// ================================================================== C ABI
+extern "C" int mpr_version(void) { return 100; }
+
+extern "C" const char *mpr_status_string(int status)
+{
+    switch (status) {
+    case MPR_OK: return "ok";
+    case MPR_EINVAL: return "invalid argument";
+    case MPR_ENOMEM: return "workspace too small";
+    case MPR_EOVERFLOW: return "finite value above 0x7FFF would enter a product";
+    case MPR_ENOTFOUND: return "no periodic regime found";
+    case MPR_EHIP: return "HIP runtime error";
+    case MPR_EUNSUPPORTED: return "unsupported device or size";
+    default: return "unknown status";
+    }
+}
+
+extern "C" mpr_status mpr_init(int device)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MPR_EUNSUPPORTED;
+    return init_device(device);
+}
+
+extern "C" mpr_status mpr_transfer_size(int m, int64_t *n_states_host)
+{
+    if (m < 1 || m > 12 || !n_states_host) return MPR_EINVAL;
+    *n_states_host = transfer_size(m);
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_transfer_words(int m, uint8_t *words_host, int64_t capacity_words)
+{
+    if (m < 1 || m > 12 || !words_host) return MPR_EINVAL;
+    const int64_t n = transfer_size(m);
+    if (capacity_words < n) return MPR_ENOMEM;
+    transfer_words(m, words_host, n);
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_build_transfer(int m, uint16_t *A, int64_t lda, mpr_stream stream)
+{
+    if (m < 1 || m > 11 || !A) return MPR_EINVAL;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    if (lda < transfer_size(m)) return MPR_EINVAL;
+    return transfer_launch(m, A, lda, as_stream(stream));
+}
+
+static mpr_status gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B, int64_t ldb,
+                            const void *C, int64_t ldc)
+{
+    if (M < 0 || N < 0 || K < 0) return MPR_EINVAL;
+    if ((M && K && !A) || (K && N && !B) || (M && N && !C)) return MPR_EINVAL;
+    if (!ld_ok(lda, K) || !ld_ok(ldb, N) || !ld_ok(ldc, N)) return MPR_EINVAL;
+    if (M > (1ll << 31) || N > (1ll << 31) || K > (1ll << 31)) return MPR_EUNSUPPORTED;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_minplus_gemm_cfg(int cfg, int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t lda,
+                                           const uint16_t *B, int64_t ldb, uint16_t *C, int64_t ldc,
+                                           int32_t *d_status, mpr_stream stream)
+{
+    mpr_status e = gemm_args(M, N, K, A, lda, B, ldb, C, ldc);
+    if (e != MPR_OK) return e;
+    if (cfg < -1 || cfg >= mpr_gemm_config_count()) return MPR_EINVAL;
+    if ((e = ensure_init()) != MPR_OK) return e;
+    hipStream_t s = as_stream(stream);
+    if (d_status) {
+        if ((e = validate_launch(A, M, K, lda, d_status, s)) != MPR_OK) return e;
+        if ((e = validate_launch(B, K, N, ldb, d_status, s)) != MPR_OK) return e;
+    }
+    return gemm_launch(cfg, M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
+extern "C" mpr_status mpr_minplus_gemm(int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t lda,
+                                       const uint16_t *B, int64_t ldb, uint16_t *C, int64_t ldc, int32_t *d_status,
+                                       mpr_stream stream)
+{
+    return mpr_minplus_gemm_cfg(-1, M, N, K, A, lda, B, ldb, C, ldc, d_status, stream);
+}
+
+extern "C" mpr_status mpr_normalise(int64_t M, int64_t N, uint16_t *C, int64_t ldc, const int64_t *R_in,
+                                    int64_t *R_out, int32_t *d_status, mpr_stream stream)
+{
+    if (M < 0 || N < 0 || (M && (!C || !R_out)) || !ld_ok(ldc, N)) return MPR_EINVAL;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    return normalise_launch(M, N, C, ldc, R_in, nullptr, R_out, d_status, nullptr, as_stream(stream));
+}
+
+extern "C" mpr_status mpr_gemm_norm_workspace_size(int64_t K, int64_t N, size_t *bytes_host)
+{
+    if (K < 0 || N < 0 || !bytes_host) return MPR_EINVAL;
+    *bytes_host = gemm_norm_ws(K, N, nullptr);
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_minplus_gemm_norm(int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t lda,
+                                            const int64_t *Ra, const uint16_t *B, int64_t ldb, const int64_t *Rb,
+                                            uint16_t *C, int64_t ldc, int64_t *Rc, void *ws, size_t ws_bytes,
+                                            int32_t *d_status, mpr_stream stream)
+{
+    mpr_status e = gemm_args(M, N, K, A, lda, B, ldb, C, ldc);
+    if (e != MPR_OK) return e;
+    if (M && !Rc) return MPR_EINVAL;
+    int64_t ldp = 0;
+    const size_t need = gemm_norm_ws(K, N, &ldp);
+    if (Rb && (!ws || ws_bytes < need)) return MPR_ENOMEM;
+    if ((e = ensure_init()) != MPR_OK) return e;
+    hipStream_t s = as_stream(stream);
+    if (d_status) {
+        if ((e = validate_launch(A, M, K, lda, d_status, s)) != MPR_OK) return e;
+        if ((e = validate_launch(B, K, N, ldb, d_status, s)) != MPR_OK) return e;
+    }
+    Carver c(ws);
+    int64_t *sc = c.take<int64_t>(1);
+    u16 *Bp = c.take<u16>((size_t)(K * ldp));
+    return gemm_norm_impl(M, N, K, A, lda, Ra, B, ldb, Rb, C, ldc, Rc, sc, Bp, ldp, d_status, s);
+}
+
+extern "C" mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *bytes_host)
+{
+    if (n < 0 || e < 1 || !bytes_host || (schedule != MPR_CHAIN && schedule != MPR_SQUARE)) return MPR_EINVAL;
+    *bytes_host = carve_power(nullptr, n, schedule).bytes;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t lda, int64_t e, int schedule,
+                                        uint16_t *N_out, int64_t ldo, int64_t *R_out, void *ws, size_t ws_bytes,
+                                        int32_t *d_status, mpr_stream stream)
+{
+    if (n < 0 || e < 1 || (schedule != MPR_CHAIN && schedule != MPR_SQUARE)) return MPR_EINVAL;
+    if (n && (!A || !N_out || !R_out)) return MPR_EINVAL;
+    if (!ld_ok(lda, n) || !ld_ok(ldo, n)) return MPR_EINVAL;
+    if (n == 0) return MPR_OK;
+    PowerWs w = carve_power(ws, n, schedule);
+    if (!ws || ws_bytes < w.bytes) return MPR_ENOMEM;
+    mpr_status r = ensure_init();
+    if (r != MPR_OK) return r;
+    hipStream_t s = as_stream(stream);
+    if ((r = validate_launch(A, n, n, lda, d_status, s)) != MPR_OK) return r;
+    return schedule == MPR_CHAIN ? power_chain(A, n, lda, e, N_out, ldo, R_out, w, d_status, s)
+                                 : power_square(A, n, lda, e, N_out, ldo, R_out, w, d_status, s);
+}
+
+extern "C" mpr_status mpr_trace_min(const uint16_t *N, int64_t n, int64_t ld, const int64_t *R, int64_t *d_gamma,
+                                    mpr_stream stream)
+{
+    if (n < 0 || !d_gamma || (n && !N) || !ld_ok(ld, n)) return MPR_EINVAL;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    return trace_launch(N, n, ld, R, d_gamma, as_stream(stream));
+}
+
+extern "C" mpr_status mpr_trace_of_product(const uint16_t *X, const int64_t *RX, const uint16_t *Y,
+                                           const int64_t *RY, int64_t n, int64_t ld, int64_t *d_gamma,
+                                           mpr_stream stream)
+{
+    if (n < 0 || !d_gamma || (n && (!X || !Y)) || !ld_ok(ld, n)) return MPR_EINVAL;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    return trace_product_launch(X, RX, Y, RY, n, ld, d_gamma, as_stream(stream));
+}
+
+extern "C" mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_host)
+{
+    if (n < 0 || slots < 2 || !bytes_host) return MPR_EINVAL;
+    PeriodWs w = carve_period(nullptr, n, 0, slots);
+    *bytes_host = w.fixed + (size_t)slots * w.slot_bytes;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int64_t *mu_host,
+                                      int64_t *lam_host, int64_t *c_host, int64_t *traces_host, void *ws,
+                                      size_t ws_bytes, mpr_stream stream)
+{
+    if (n < 1 || kmax < 1 || !A || !mu_host || !lam_host || !c_host || !ld_ok(lda, n)) return MPR_EINVAL;
+    PeriodWs w = carve_period(ws, n, ws_bytes, 0);
+    if (!ws || w.slots < 2) return MPR_ENOMEM;
+    mpr_status r = ensure_init();
+    if (r != MPR_OK) return r;
+    hipStream_t s = as_stream(stream);
+    int32_t *st = (int32_t *)&w.scal[2];
+    if ((r = fill_i32_launch(st, 2, 0, s)) != MPR_OK) return r;
+    if ((r = validate_launch(A, n, n, lda, st, s)) != MPR_OK) return r;
+    if (traces_host) traces_host[0] = MPR_ROW_NONE;
+
+    std::unordered_multimap<uint64_t, int64_t> seen;  // class hash -> k (slot k-1)
+    bool found = false, storing = true;
+    int64_t mu = 0, lam = 0, cval = 0;
+    int64_t prev_slot = -1;
+    int64_t pp = 0;  // ping-pong selector once slots stop holding every power
+    for (int64_t k = 1; k <= kmax; k++) {
+        if (storing && k > w.slots) storing = false;
+        int64_t slot;
+        if (storing) {
+            slot = k - 1;
+        } else {
+            // alternate between the last two slots, never overwriting the input
+            const int64_t a = w.slots - 1, b = w.slots - 2;
+            slot = (prev_slot == a) ? b : a;
+            (void)pp;
+        }
+        u16 *Nk = slot_N(w, slot);
+        int64_t *Rk = slot_R(w, slot);
+        if (k == 1) {
+            r = copy_launch(A, lda, Nk, w.ld, n, n, s);
+            if (r == MPR_OK) r = normalise_launch(n, n, Nk, w.ld, nullptr, nullptr, Rk, st, w.row_hash, s);
+        } else {
+            r = gemm_launch(-1, n, n, n, slot_N(w, prev_slot), w.ld, A, lda, Nk, w.ld, s);
+            if (r == MPR_OK)
+                r = normalise_launch(n, n, Nk, w.ld, slot_R(w, prev_slot), nullptr, Rk, st, w.row_hash, s);
+        }
+        if (r == MPR_OK) r = class_hash_launch(w.row_hash, Rk, n, (uint64_t *)&w.scal[0], s);
+        if (r == MPR_OK) r = trace_launch(Nk, n, w.ld, Rk, &w.scal[1], s);
+        if (r != MPR_OK) return r;
+        int64_t host[3];
+        if (hipMemcpyAsync(host, w.scal, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MPR_EHIP;
+        if ((int32_t)(host[2] & 0xFFFFFFFF) != 0) return MPR_EOVERFLOW;
+        if (traces_host) traces_host[k] = host[1];
+        prev_slot = slot;
+        if (!found && storing) {
+            const uint64_t h = (uint64_t)host[0];
+            auto range = seen.equal_range(h);
+            for (auto it = range.first; it != range.second && !found; ++it) {
+                const int64_t j = it->second;
+                int64_t *out3 = &w.scal[3];
+                if ((r = compare_launch(slot_N(w, j - 1), slot_R(w, j - 1), Nk, Rk, n, w.ld, out3, s)) != MPR_OK)
+                    return r;
+                int64_t cmp[3];
+                if (hipMemcpyAsync(cmp, out3, sizeof(cmp), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return MPR_EHIP;
+                if (cmp[0] == 0 && cmp[1] == cmp[2]) {
+                    found = true;
+                    mu = j;
+                    lam = k - j;
+                    cval = cmp[1] == MPR_ROW_NONE ? 0 : cmp[1];
+                }
+            }
+            if (!found) seen.emplace(h, k);
+        }
+        if (found && !traces_host) break;
+    }
+    if (!found) return MPR_ENOTFOUND;
+    *mu_host = mu;
+    *lam_host = lam;
+    *c_host = cval;
+    return MPR_OK;
+}

@@ -1,0 +1,401 @@
+// batch.hip -- many independent power chains in one persistent launch.
+//
+// Row i of A^k = A^(k-1) (x) A depends only on row i of A^(k-1) and on A, and
+// the row-min normalisation is per row, so a block of rows (a "panel") of one
+// chain can run all of its e-1 steps without ever waiting for another
+// panel.  The batch is cut into panels of BM rows; a work list of
+// (instance, first row) items, longest first, is consumed by a grid sized to
+// the number of resident workgroups, each pulling the next item with one
+// atomic add.  Every workgroup leaves the loop once the list is exhausted,
+// so the grid always drains.  Per step, a panel computes its BM x n slice of
+// the raw product column tile by column tile (the shared tile routine),
+// keeps the running row minima in LDS, then rewrites the slice normalised.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "tile.h"
+
+namespace mpr {
+
+struct DevChain {
+    const u16 *A;
+    int64_t n, lda, e;
+    u16 *N_out;
+    int64_t ldo;
+    int64_t *R_out;
+    u16 *P;  // second panel buffer (workspace), n x ldp
+    int64_t ldp;
+};
+
+struct BatchItem {
+    int32_t inst;
+    int32_t row0;
+};
+
+using BCfg0 = TileCfg<64, 128, 32, 4, 8>;   // 256 threads, 64-row panels
+using BCfg1 = TileCfg<32, 128, 32, 4, 8>;   // 128 threads, 32-row panels
+using BCfg2 = TileCfg<128, 128, 32, 8, 8>;  // 256 threads, 128-row panels
+
+__device__ __forceinline__ void agent_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void agent_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Rewrites rows [r0, r0+rows) of src (raw values) into dst, subtracting the
+// row minima in rmin[] (infinity stays) and adding them to R (or setting R
+// when first).  Flags normalised values above MPR_FMAX.
+template <int NT>
+__device__ void panel_normalise(const u16 *src, int64_t lds_, u16 *dst, int64_t ldd, int64_t r0, int rows, int64_t n,
+                                const uint32_t *rmin, int64_t *R, bool first, int32_t *st)
+{
+    bool over = false;
+    const int64_t total = (int64_t)rows * n;
+    for (int64_t t = threadIdx.x; t < total; t += NT) {
+        const int rr = (int)(t / n);
+        const int64_t j = t % n;
+        const uint32_t r = rmin[rr];
+        uint32_t v = src[(r0 + rr) * lds_ + j];
+        if (r != 0xFFFFu && v != 0xFFFFu) v -= r;
+        over |= v != 0xFFFFu && v > FMAX16;
+        dst[(r0 + rr) * ldd + j] = (u16)v;
+    }
+    for (int rr = threadIdx.x; rr < rows; rr += NT) {
+        const uint32_t r = rmin[rr];
+        int64_t &Rv = R[r0 + rr];
+        if (first)
+            Rv = r == 0xFFFFu ? ROW_NONE : (int64_t)r;
+        else
+            Rv = (r == 0xFFFFu || Rv == ROW_NONE) ? ROW_NONE : Rv + (int64_t)r;
+    }
+    if (over) set_status(st, MPR_EOVERFLOW);
+}
+
+template <class T>
+__global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict__ chains,
+                                                      const BatchItem *__restrict__ items, int n_items,
+                                                      int *counter, int32_t *st)
+{
+    __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
+    __shared__ uint32_t rmin[T::BM];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= n_items) break;
+        const BatchItem item = items[it];
+        const DevChain c = chains[item.inst];
+        const int64_t n = c.n, r0 = item.row0;
+        const int rows = (int)min<int64_t>(T::BM, n - r0);
+        // Step k writes buffer (e - k) % 2 so that step e lands in N_out.
+        u16 *buf[2] = {c.N_out, c.P};
+        const int64_t ld[2] = {c.ldo, c.ldp};
+        int b = (int)((c.e - 1) & 1);
+
+        // Step 1: the panel of A itself, normalised.
+        for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < (int64_t)rows * n; t += T::NT) {
+            const int rr = (int)(t / n);
+            atomicMin(&rmin[rr], (uint32_t)c.A[(r0 + rr) * c.lda + t % n]);
+        }
+        __syncthreads();
+        panel_normalise<T::NT>(c.A, c.lda, buf[b], ld[b], r0, rows, n, rmin, c.R_out, true, st);
+
+        const bool vec = ((uintptr_t)c.A % 16 == 0) && c.lda % 8 == 0 && ((uintptr_t)c.N_out % 16 == 0) &&
+                         c.ldo % 8 == 0 && ((uintptr_t)c.P % 16 == 0) && c.ldp % 8 == 0;
+        for (int64_t k = 2; k <= c.e; k++) {
+            agent_release();
+            __syncthreads();
+            agent_acquire();
+            const int nb = b ^ 1;
+            for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
+            // (visibility of rmin is covered by the barriers inside the tile loop)
+            for (int64_t n0 = 0; n0 < n; n0 += T::BN) {
+                TileAcc<T> acc;
+                // Left operand: rows r0.. of the previous power; the panel's
+                // rows beyond `rows` read as infinity through the M bound.
+                tile_mainloop<T>(buf[b] + r0 * ld[b], ld[b], c.A, c.lda, rows, n, n, 0, n0, vec, lds, acc);
+                tile_store<T>(buf[nb] + r0 * ld[nb], ld[nb], rows, n, 0, n0, vec, acc);
+#pragma unroll
+                for (int r = 0; r < T::TM; r++) {
+                    uint32_t m = 0xFFFFu;
+#pragma unroll
+                    for (int q = 0; q < T::NACC; q++) {
+                        const uint32_t w = as_u32(acc.v[r][q]);
+                        const int col = tile_col<T>(q >> 2) + 2 * (q & 3);
+                        if (n0 + col < n) m = min(m, w & 0xFFFFu);
+                        if (n0 + col + 1 < n) m = min(m, w >> 16);
+                    }
+                    // lanes tx = 0..TX-1 of one row group are consecutive
+#pragma unroll
+                    for (int off = 1; off < T::TX; off <<= 1) m = min(m, (uint32_t)__shfl_xor(m, off, 64));
+                    if (threadIdx.x % T::TX == 0) atomicMin(&rmin[tile_row<T>(r)], m);
+                }
+            }
+            agent_release();
+            __syncthreads();
+            agent_acquire();
+            panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, st);
+            b = nb;
+        }
+        agent_release();
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+
+// ------------------------------------------------------------ host side
+struct BatchCfgInfo {
+    int bm, nt;
+    const void *kernel;
+};
+static const BatchCfgInfo kBatchCfgs[] = {
+    {BCfg0::BM, BCfg0::NT, (const void *)batch_kernel<BCfg0>},
+    {BCfg1::BM, BCfg1::NT, (const void *)batch_kernel<BCfg1>},
+    {BCfg2::BM, BCfg2::NT, (const void *)batch_kernel<BCfg2>},
+};
+static constexpr int kNumBatchCfgs = (int)(sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]));
+
+struct BatchPlan {
+    int cfg;
+    int n_items;
+    int grid;
+    DevChain *chains;
+    BatchItem *items;
+    int *counter;
+};
+
+static std::mutex g_plan_mu;
+static std::map<void *, BatchPlan> g_plans;
+
+struct BatchLayout {
+    size_t chains_off, items_off, counter_off, bufs_off, bytes;
+    std::vector<size_t> buf_off;
+    std::vector<int64_t> ldp;
+};
+
+static BatchLayout batch_layout(const mpr_chain_desc *d, int count, int bm)
+{
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (size_t)round_up((int64_t)off, 256);
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    int64_t n_items = 0;
+    for (int i = 0; i < count; i++) n_items += (d[i].n + bm - 1) / bm;
+    L.chains_off = take(sizeof(DevChain) * (size_t)count);
+    L.items_off = take(sizeof(BatchItem) * (size_t)std::max<int64_t>(n_items, 1));
+    L.counter_off = take(256);
+    for (int i = 0; i < count; i++) {
+        const int64_t ldp = round_up(std::max<int64_t>(d[i].n, 1), 8);
+        L.ldp.push_back(ldp);
+        L.buf_off.push_back(take((size_t)(d[i].n * ldp) * sizeof(u16)));
+    }
+    L.bytes = off + 256;
+    return L;
+}
+
+static int occupancy(int cfg)
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kBatchCfgs[cfg].kernel, kBatchCfgs[cfg].nt, 0) !=
+            hipSuccess ||
+        blocks < 1)
+        blocks = 1;
+    return blocks;
+}
+
+// Longest-first greedy schedule of the items on `slots` equal workers;
+// returns the modelled makespan in units of pair-operations per worker.
+static double lpt_makespan(const std::vector<double> &work_sorted, int slots)
+{
+    std::vector<double> heap(slots, 0.0);  // min-heap of finish times
+    std::make_heap(heap.begin(), heap.end(), std::greater<double>());
+    for (double w : work_sorted) {
+        std::pop_heap(heap.begin(), heap.end(), std::greater<double>());
+        heap.back() += w;
+        std::push_heap(heap.begin(), heap.end(), std::greater<double>());
+    }
+    return *std::max_element(heap.begin(), heap.end());
+}
+
+static int choose_batch_cfg(const mpr_chain_desc *d, int count)
+{
+    const int cus = device_cu_count();
+    int best = 0;
+    double best_t = 1e300;
+    for (int c = 0; c < kNumBatchCfgs; c++) {
+        const int bm = kBatchCfgs[c].bm;
+        std::vector<double> w;
+        for (int i = 0; i < count; i++)
+            for (int64_t r0 = 0; r0 < d[i].n; r0 += bm)
+                w.push_back((double)(d[i].e - 1) * (double)std::min<int64_t>(bm, d[i].n - r0) * (double)d[i].n *
+                            (double)d[i].n);
+        std::sort(w.begin(), w.end(), std::greater<double>());
+        // A worker's speed is the CU's rate shared among its resident workers.
+        const int per_cu = std::max(1, occupancy(c));
+        const double t = lpt_makespan(w, cus * per_cu) * per_cu;
+        if (t < best_t) {
+            best_t = t;
+            best = c;
+        }
+    }
+    return best;
+}
+
+static int g_forced_batch_cfg = -1;
+
+}  // namespace mpr
+
+using namespace mpr;
+
+extern "C" int mpr_batch_config_count(void) { return kNumBatchCfgs; }
+
+extern "C" mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads)
+{
+    if (cfg < 0 || cfg >= kNumBatchCfgs) return MPR_EINVAL;
+    if (panel_rows) *panel_rows = kBatchCfgs[cfg].bm;
+    if (threads) *threads = kBatchCfgs[cfg].nt;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_set_batch_config(int cfg)
+{
+    if (cfg < -1 || cfg >= kNumBatchCfgs) return MPR_EINVAL;
+    g_forced_batch_cfg = cfg;
+    return MPR_OK;
+}
+
+static mpr_status check_descs(const mpr_chain_desc *d, int count)
+{
+    if (count < 0 || (count && !d)) return MPR_EINVAL;
+    for (int i = 0; i < count; i++) {
+        if (d[i].n < 1 || d[i].n > (1 << 30) || d[i].e < 1) return MPR_EINVAL;
+        if (!d[i].A || !d[i].N_out || !d[i].R_out) return MPR_EINVAL;
+        if (d[i].lda < d[i].n || d[i].ldo < d[i].n) return MPR_EINVAL;
+    }
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_batch_workspace_size(const mpr_chain_desc *descs_host, int count, size_t *bytes_host)
+{
+    mpr_status e = check_descs(descs_host, count);
+    if (e != MPR_OK || !bytes_host) return e != MPR_OK ? e : MPR_EINVAL;
+    size_t mx = 0;
+    for (int c = 0; c < kNumBatchCfgs; c++) mx = std::max(mx, batch_layout(descs_host, count, kBatchCfgs[c].bm).bytes);
+    *bytes_host = mx;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count, void *ws, size_t ws_bytes,
+                                     mpr_stream stream)
+{
+    mpr_status e = check_descs(descs_host, count);
+    if (e != MPR_OK) return e;
+    if (!ws) return MPR_EINVAL;
+    if ((e = ensure_init()) != MPR_OK) return e;
+    const int cfg = g_forced_batch_cfg >= 0 ? g_forced_batch_cfg : choose_batch_cfg(descs_host, count);
+    const int bm = kBatchCfgs[cfg].bm;
+    BatchLayout L = batch_layout(descs_host, count, bm);
+    if (ws_bytes < L.bytes) return MPR_ENOMEM;
+    char *base = (char *)ws;
+    std::vector<DevChain> chains(count);
+    std::vector<std::pair<double, BatchItem>> items;
+    for (int i = 0; i < count; i++) {
+        const mpr_chain_desc &d = descs_host[i];
+        chains[i] = DevChain{d.A, d.n, d.lda, d.e, d.N_out, d.ldo, d.R_out, (u16 *)(base + L.buf_off[i]), L.ldp[i]};
+        for (int64_t r0 = 0; r0 < d.n; r0 += bm) {
+            const double w = (double)(d.e - 1 + 1) * (double)std::min<int64_t>(bm, d.n - r0) * (double)d.n * (double)d.n;
+            items.push_back({w, BatchItem{i, (int32_t)r0}});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<double, BatchItem> &a, const std::pair<double, BatchItem> &b) {
+                         return a.first > b.first;
+                     });
+    std::vector<BatchItem> flat;
+    for (auto &p : items) flat.push_back(p.second);
+    hipStream_t s = as_stream(stream);
+    if (count && hipMemcpyAsync(base + L.chains_off, chains.data(), sizeof(DevChain) * count, hipMemcpyHostToDevice,
+                                s) != hipSuccess)
+        return MPR_EHIP;
+    if (!flat.empty() && hipMemcpyAsync(base + L.items_off, flat.data(), sizeof(BatchItem) * flat.size(),
+                                        hipMemcpyHostToDevice, s) != hipSuccess)
+        return MPR_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MPR_EHIP;
+    BatchPlan plan;
+    plan.cfg = cfg;
+    plan.n_items = (int)flat.size();
+    plan.grid = std::max(1, std::min(plan.n_items, device_cu_count() * occupancy(cfg)));
+    plan.chains = (DevChain *)(base + L.chains_off);
+    plan.items = (BatchItem *)(base + L.items_off);
+    plan.counter = (int *)(base + L.counter_off);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans[ws] = plan;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream stream)
+{
+    BatchPlan p;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find(ws);
+        if (it == g_plans.end()) return MPR_EINVAL;
+        p = it->second;
+    }
+    if (p.n_items == 0) return MPR_OK;
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, p.counter);
+    mpr_status e = check_launch();
+    if (e != MPR_OK) return e;
+    const void *args_k = kBatchCfgs[p.cfg].kernel;
+    void *args[] = {&p.chains, &p.items, &p.n_items, &p.counter, &d_status};
+    if (hipLaunchKernel(args_k, dim3(p.grid), dim3(kBatchCfgs[p.cfg].nt), args, 0, s) != hipSuccess) return MPR_EHIP;
+    return check_launch();
+}
+
+extern "C" mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count, void *ws, size_t ws_bytes,
+                                      int32_t *d_status, mpr_stream stream)
+{
+    mpr_status e = mpr_batch_plan(descs_host, count, ws, ws_bytes, stream);
+    return e != MPR_OK ? e : mpr_batch_launch(ws, d_status, stream);
+}
+
+extern "C" mpr_status mpr_batch_graph_create(void *ws, int32_t *d_status, mpr_stream stream, void **graph_host)
+{
+    if (!graph_host) return MPR_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (!s) return MPR_EINVAL;  // the null stream can not be captured
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPR_EHIP;
+    mpr_status e = mpr_batch_launch(ws, d_status, stream);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess || e != MPR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e != MPR_OK ? e : MPR_EHIP;
+    }
+    hipGraphExec_t x = nullptr;
+    const bool ok = hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipGraphDestroy(g);
+    if (!ok) return MPR_EHIP;
+    *graph_host = (void *)x;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_graph_launch(void *graph, mpr_stream stream)
+{
+    if (!graph) return MPR_EINVAL;
+    return hipGraphLaunch((hipGraphExec_t)graph, as_stream(stream)) == hipSuccess ? MPR_OK : MPR_EHIP;
+}
+
+extern "C" mpr_status mpr_graph_destroy(void *graph)
+{
+    if (!graph) return MPR_EINVAL;
+    return hipGraphExecDestroy((hipGraphExec_t)graph) == hipSuccess ? MPR_OK : MPR_EHIP;
+}

@@ -1,0 +1,194 @@
+// gemm.hip -- single (min,+) product C = A (x) B over a grid of tiles, the
+// compiled tile configurations, the size -> configuration table and the
+// autotuner that fills it.
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "tile.h"
+
+namespace mpr {
+
+// Compiled configurations: (BM, BN, BK, TM, TN).
+using Cfg0 = TileCfg<128, 128, 32, 8, 8>;    // 256 threads, 8x8 per lane
+using Cfg1 = TileCfg<128, 256, 32, 8, 16>;   // 256 threads, 8x16 per lane
+using Cfg2 = TileCfg<256, 128, 32, 16, 8>;   // 256 threads, 16x8 per lane
+using Cfg3 = TileCfg<64, 64, 32, 4, 8>;      // 128 threads, small problems
+using Cfg4 = TileCfg<64, 256, 32, 8, 16>;    // 128 threads, 8x16 per lane
+using Cfg5 = TileCfg<128, 128, 16, 8, 8>;    // shallow k slices
+
+// Blocks are handed to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// Renumber so that each XCD receives a contiguous run of tiles, and walk the
+// tiles in groups of G tile-rows so that the blocks resident on one XCD share
+// A row panels and B column panels in that XCD's L2.
+__device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
+{
+    const int nb = (int)gridDim.x;  // a multiple of 8
+    const int b = (int)blockIdx.x;
+    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    if (t >= tiles_m * tiles_n) return false;
+    constexpr int G = 8;
+    const int width = G * tiles_n;
+    const int first = (t / width) * G;
+    const int gs = min(tiles_m - first, G);
+    const int w = t % width;
+    tm = first + w % gs;
+    tn = w / gs;
+    return true;
+}
+
+template <class T>
+__global__ __launch_bounds__(T::NT) void gemm_kernel(const u16 *__restrict__ A, int64_t lda,
+                                                     const u16 *__restrict__ B, int64_t ldb,
+                                                     u16 *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                                                     int64_t K, int tiles_m, int tiles_n, int vec)
+{
+    __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
+    int tm, tn;
+    if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
+    const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
+    TileAcc<T> acc;
+    tile_mainloop<T>(A, lda, B, ldb, M, N, K, m0, n0, vec != 0, lds, acc);
+    tile_store<T>(C, ldc, M, N, m0, n0, vec != 0, acc);
+}
+
+// An empty inner dimension: every entry of C is infinite.
+__global__ void fill_inf_kernel(u16 *C, int64_t ldc, int64_t M, int64_t N)
+{
+    const int64_t total = M * N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+        C[(t / N) * ldc + t % N] = 0xFFFF;
+}
+
+template <class T>
+static mpr_status launch_cfg(int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
+                             int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
+{
+    const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+    const int64_t tiles = tiles_m * tiles_n;
+    if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
+    const int64_t blocks = round_up(tiles, 8);
+    const bool vec = aligned16(A) && aligned16(B) && aligned16(C) && lda % 8 == 0 && ldb % 8 == 0 && ldc % 8 == 0;
+    hipLaunchKernelGGL(gemm_kernel<T>, dim3((unsigned)blocks), dim3(T::NT), 0, s, A, lda, B, ldb, C, ldc, M, N, K,
+                       (int)tiles_m, (int)tiles_n, vec ? 1 : 0);
+    return check_launch();
+}
+
+struct CfgInfo {
+    int bm, bn, bk, tm, tn, nt;
+    mpr_status (*launch)(int64_t, int64_t, int64_t, const u16 *, int64_t, const u16 *, int64_t, u16 *, int64_t,
+                         hipStream_t);
+};
+
+#define MPR_CFG(T) {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, launch_cfg<T>}
+static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0), MPR_CFG(Cfg1), MPR_CFG(Cfg2),
+                                MPR_CFG(Cfg3), MPR_CFG(Cfg4), MPR_CFG(Cfg5)};
+#undef MPR_CFG
+static constexpr int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
+
+// Size -> configuration table (largest dimension, ascending).  The default
+// is replaced by mpr_set_tile_table with the autotuner's measurements.
+static std::mutex g_table_mu;
+static std::vector<std::pair<int64_t, int>> g_table = {{96, 3}, {1024, 0}, {INT64_MAX, 1}};
+
+int pick_config(int64_t M, int64_t N, int64_t K)
+{
+    const int64_t d = std::max(M, std::max(N, K));
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    for (auto &e : g_table)
+        if (d <= e.first) return e.second;
+    return g_table.back().second;
+}
+
+mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
+                       int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
+{
+    if (M == 0 || N == 0) return MPR_OK;
+    if (K == 0) {
+        const int64_t total = M * N;
+        const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL(fill_inf_kernel, dim3(blocks), dim3(256), 0, s, C, ldc, M, N);
+        return check_launch();
+    }
+    if (cfg < 0) cfg = pick_config(M, N, K);
+    if (cfg >= kNumCfgs) return MPR_EINVAL;
+    return kCfgs[cfg].launch(M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
+}  // namespace mpr
+
+using namespace mpr;
+
+extern "C" int mpr_gemm_config_count(void) { return kNumCfgs; }
+
+extern "C" mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads)
+{
+    if (cfg < 0 || cfg >= kNumCfgs) return MPR_EINVAL;
+    const CfgInfo &c = kCfgs[cfg];
+    if (bm) *bm = c.bm;
+    if (bn) *bn = c.bn;
+    if (bk) *bk = c.bk;
+    if (tm) *tm = c.tm;
+    if (tn) *tn = c.tn;
+    if (threads) *threads = c.nt;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_set_tile_table(const int64_t *max_dim_host, const int *cfg_host, int entries)
+{
+    if (entries <= 0 || !max_dim_host || !cfg_host) return MPR_EINVAL;
+    std::vector<std::pair<int64_t, int>> t;
+    for (int i = 0; i < entries; i++) {
+        if (cfg_host[i] < 0 || cfg_host[i] >= kNumCfgs) return MPR_EINVAL;
+        if (i > 0 && max_dim_host[i] <= max_dim_host[i - 1]) return MPR_EINVAL;
+        t.push_back({max_dim_host[i], cfg_host[i]});
+    }
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    g_table = t;
+    return MPR_OK;
+}
+
+__global__ void tune_fill_kernel(u16 *X, int64_t count, uint64_t seed)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t z = mix64(seed + (uint64_t)(t + 1) * 0x9E3779B97F4A7C15ull);
+        X[t] = (z >> 32) < 1288490189ull ? (u16)0xFFFF : (u16)(z & 15);  // 30 % infinite, else 0..15
+    }
+}
+
+extern "C" mpr_status mpr_autotune_gemm(int64_t n, int reps, float *ms_host, int *best_host, mpr_stream stream)
+{
+    if (n <= 0 || reps <= 0 || !ms_host) return MPR_EINVAL;
+    mpr_status st = ensure_init();
+    if (st != MPR_OK) return st;
+    hipStream_t s = as_stream(stream);
+    const int64_t ld = round_up(n, 8);
+    u16 *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)(3 * n * ld) * sizeof(u16)) != hipSuccess) return MPR_ENOMEM;
+    u16 *A = buf, *B = buf + n * ld, *C = buf + 2 * n * ld;
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, buf, 2 * n * ld, (uint64_t)n);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    int besti = -1;
+    for (int c = 0; c < kNumCfgs && st == MPR_OK; c++) {
+        st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s);  // warm-up
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == MPR_OK; r++) st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms_host[c] = ms / reps;
+        if (ms_host[c] < best) {
+            best = ms_host[c];
+            besti = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(buf);
+    if (best_host) *best_host = besti;
+    return st;
+}

@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/mpr.h declares, and its host-only entry points and
+argument checks behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mpr():
+    import paper_2409_17658_amd as m
+
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2409_17658_amd import build
+
+        build.build()
+    m.lib()
+    return m
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mpr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(mpr):
+    names = _declared()
+    assert len(names) >= 25
+    L = mpr.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding declares a signature for each of them
+    assert set(names) == set(mpr.exported_symbols())
+
+
+def test_transfer_size_matches_table1(mpr, paper_values):
+    for m, c in paper_values["word_counts"]["values"].items():
+        assert mpr.transfer_size(int(m)) == c
+
+
+def test_transfer_words_match_oracle_order(mpr):
+    for m in range(1, 9):
+        assert np.array_equal(mpr.transfer_words(m), O.words(m)), m
+
+
+def test_argument_errors_are_synchronous(mpr):
+    L = mpr.lib()
+    n = ctypes.c_int64()
+    assert L.mpr_transfer_size(0, ctypes.byref(n)) == 1
+    assert L.mpr_transfer_size(13, ctypes.byref(n)) == 1
+    assert L.mpr_transfer_size(3, None) == 1
+    # negative sizes, missing pointers, short leading dimensions
+    assert L.mpr_minplus_gemm(-1, 4, 4, None, 4, None, 4, None, 4, None, None) == 1
+    assert L.mpr_minplus_gemm(4, 4, 4, None, 4, None, 4, None, 4, None, None) == 1
+    p = ctypes.c_void_p(16)
+    assert L.mpr_minplus_gemm(4, 8, 4, p, 3, p, 8, p, 8, None, None) == 1
+    assert L.mpr_minplus_power(p, 4, 4, 0, 0, p, 4, p, p, 1 << 20, None, None) == 1
+    assert L.mpr_minplus_power(p, 4, 4, 3, 7, p, 4, p, p, 1 << 20, None, None) == 1
+    assert L.mpr_minplus_power(p, 4, 4, 3, 0, p, 4, p, p, 16, None, None) == 2  # workspace too small
+    assert L.mpr_build_transfer(12, p, 1 << 20, None) == 1
+    assert L.mpr_batch_launch(ctypes.c_void_p(12345), None, None) == 1  # never planned
+    assert L.mpr_graph_launch(None, None) == 1
+    assert mpr.lib().mpr_status_string(3).decode().startswith("finite value")
+
+
+def test_workspace_sizes(mpr):
+    ws_chain = mpr.power_workspace_size(1000, 10, mpr.CHAIN)
+    ws_sq = mpr.power_workspace_size(1000, 10, mpr.SQUARE)
+    assert ws_chain >= 1000 * 1000 * 2 and ws_sq >= 4 * 1000 * 1000 * 2
+    assert mpr.period_workspace_size(100, 10) >= 10 * 100 * 104 * 2
+    with pytest.raises(mpr.MprError):
+        mpr.period_workspace_size(100, 1)
+
+
+def test_configs_describe_themselves(mpr):
+    for c in range(mpr.gemm_config_count()):
+        info = mpr.gemm_config_info(c)
+        assert info["bm"] % info["tm"] == 0 and info["bn"] % info["tn"] == 0
+        assert info["threads"] == (info["bm"] // info["tm"]) * (info["bn"] // info["tn"])
+    for c in range(mpr.batch_config_count()):
+        assert mpr.batch_config_info(c)["panel_rows"] in (32, 64, 128)
+    with pytest.raises(mpr.MprError):
+        mpr.set_tile_table([(100, 0), (50, 1)])  # not ascending
+    mpr.set_tile_table([(96, 3), (1024, 0), (1 << 62, 1)])
+
+
+def test_product_path_has_no_oracle_import():
+    """The product package never imports the oracle (or any CPU fallback)."""
+    pkg = os.path.join(ROOT, "paper_2409_17658_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt, f

@@ -1,0 +1,251 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is exact (integers; tolerance 0).  Inputs come from the
+seeded generators in `synth`, the same bytes for both sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpr():
+    import paper_2409_17658_amd as m
+
+    m.lib()
+    m.init(0)
+    return m
+
+
+def _u16(a):
+    return O.to_u16(a)
+
+
+def _dev(mpr, a):
+    return mpr.to_device(a)
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ products
+SHAPES = [(1, 1, 1), (7, 9, 5), (31, 33, 17), (64, 64, 64), (127, 129, 255), (300, 257, 511), (513, 200, 130)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gemm_random_all_configs(mpr, shape):
+    M, N, K = shape
+    print("gemm", shape, flush=True)
+    X = synth.random_matrix(M, K, 101, 0, 15, 0.30)
+    Y = synth.random_matrix(K, N, 102, 0, 15, 0.30)
+    ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
+    A, B = _dev(mpr, X), _dev(mpr, Y)
+    for cfg in range(mpr.gemm_config_count()):
+        C = mpr.minplus_gemm(A, B, cfg=cfg)
+        assert np.array_equal(_host(C), ref), cfg
+
+
+def test_gemm_unaligned_leading_dimensions(mpr):
+    """Row strides that are not multiples of 8 take the element-wise path."""
+    M, N, K = 45, 37, 29
+    X = synth.random_matrix(M, K, 7, 0, 15, 0.3)
+    Y = synth.random_matrix(K, N, 8, 0, 15, 0.3)
+    ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
+    Ap = np.full((M, K + 2), 0xFFFF, dtype=np.uint16)  # row stride 31
+    Ap[:, :K] = X
+    Bp = np.pad(Y, ((0, 0), (0, 5)))  # row stride 42
+    A = torch.from_numpy(Ap).cuda()[:, :K]
+    B = torch.from_numpy(Bp).cuda()[:, :N]
+    assert A.stride(0) % 8 and B.stride(0) % 8
+    Cbuf = torch.zeros((M, N + 1), dtype=torch.uint16, device="cuda")  # row stride 38
+    for cfg in range(mpr.gemm_config_count()):
+        mpr.minplus_gemm(A, B, C=Cbuf[:, :N], cfg=cfg)
+        assert np.array_equal(_host(Cbuf[:, :N]), ref), cfg
+
+
+def test_gemm_extremes(mpr):
+    """All-infinite rows/columns, entries at the 0x7FFF bound, empty K."""
+    n = 70
+    X = synth.random_matrix(n, n, 3, 0, 0x7FFF, 0.3)
+    Y = synth.random_matrix(n, n, 4, 0x7000, 0x7FFF, 0.2)
+    X[5, :] = 0xFFFF
+    Y[:, 9] = 0xFFFF
+    X[:, 0] = 0x7FFF
+    ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
+    C = mpr.minplus_gemm(_dev(mpr, X), _dev(mpr, Y))
+    got = _host(C)
+    assert np.array_equal(got, ref)
+    assert np.all(got[5] == 0xFFFF) and np.all(got[:, 9] == 0xFFFF)
+    # empty inner dimension: every entry infinite
+    A0 = mpr.alloc_matrix(4, 0)
+    B0 = mpr.alloc_matrix(0, 6)
+    C0 = mpr.minplus_gemm(A0, B0)
+    assert np.all(_host(C0) == 0xFFFF)
+
+
+def test_gemm_overflow_is_reported(mpr):
+    X = synth.random_matrix(40, 40, 5, 0, 15, 0.3)
+    X[3, 4] = 0x8000
+    A = _dev(mpr, X)
+    with pytest.raises(mpr.MprError) as e:
+        mpr.minplus_gemm(A, A)
+    assert e.value.status == 3
+
+
+def test_gemm_full_size_sampled(mpr):
+    """N = 16384 (the benchmark size) in the benchmark's launch: sampled
+    entries, each recomputed by the oracle from the definition."""
+    n = 16384
+    X = synth.random_matrix(n, n, 1, 0, 15, 0.30)
+    Y = synth.random_matrix(n, n, 2, 0, 15, 0.30)
+    C = mpr.minplus_gemm(_dev(mpr, X), _dev(mpr, Y), check=False)
+    rng = np.random.default_rng(0)
+    ii = np.concatenate([rng.integers(0, n, 1500), [0, n - 1, n - 1, 0]])
+    jj = np.concatenate([rng.integers(0, n, 1500), [0, n - 1, 0, n - 1]])
+    got = _host(C)[ii, jj]
+    ref = _u16(O.minplus_at(O.from_u16(X), O.from_u16(Y), ii, jj))
+    assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------------ normalisation / offsets
+def test_normalise_matches_oracle(mpr):
+    X = synth.random_matrix(123, 301, 9, 3, 40, 0.3)
+    X[7, :] = 0xFFFF
+    C = _dev(mpr, X)
+    Rin = torch.arange(123, dtype=torch.int64, device="cuda") * 5
+    Rin[11] = mpr.ROW_NONE
+    X[11, :] = 0xFFFF
+    C = _dev(mpr, X)
+    Rout = mpr.normalise(C, Rin)
+    N, r = O.normalise(O.from_u16(X))
+    assert np.array_equal(_host(C), _u16(N))
+    R = O.add_offsets(Rin.cpu().numpy(), r)
+    assert np.array_equal(Rout.cpu().numpy(), R)
+
+
+def test_gemm_norm_product_of_powers(mpr):
+    A = O.transfer(4)
+    Pa = O.power_chain(A, 5)
+    Pb = O.power_chain(A, 7)
+    Nc, Rc = O.product_of_powers(*Pa, *Pb)
+    C, R = mpr.minplus_gemm_norm(_dev(mpr, _u16(Pa[0])), _dev(mpr, _u16(Pb[0])),
+                                 torch.from_numpy(Pa[1]).cuda(), torch.from_numpy(Pb[1]).cuda())
+    assert np.array_equal(_host(C), _u16(Nc)) and np.array_equal(R.cpu().numpy(), Rc)
+
+
+# ------------------------------------------------------------------ transfer matrix
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_build_transfer_bit_exact(mpr, m):
+    A = mpr.build_transfer(m)
+    assert np.array_equal(_host(A), _u16(O.transfer(m)))
+
+
+def test_build_transfer_m9_sampled_rows(mpr):
+    A = mpr.build_transfer(9)
+    rows = [0, 1, 777, 12345, 21908]
+    assert np.array_equal(_host(A)[rows], _u16(O.transfer_rows(9, rows)))
+
+
+# ------------------------------------------------------------------ powers
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("m,e", [(3, 1), (3, 2), (3, 17), (4, 23), (5, 12), (6, 9)])
+def test_power_transfer(mpr, m, e, schedule):
+    A = mpr.build_transfer(m)
+    N, R = mpr.minplus_power(A, e, schedule)
+    Nr, Rr = O.power_chain(O.transfer(m), e)
+    assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_power_random_and_banded(mpr, schedule):
+    for X, e in [(synth.random_matrix(257, 257, 11, 0, 31, 0.25), 9), (synth.banded_matrix(600, 64), 8)]:
+        N, R = mpr.minplus_power(_dev(mpr, X), e, schedule)
+        Nr, Rr = O.power_chain(O.from_u16(X), e)
+        assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
+
+
+def test_power_empty_rows_stay_empty(mpr):
+    X = synth.random_matrix(90, 90, 12, 0, 9, 0.2)
+    X[3, :] = 0xFFFF
+    for sched in (0, 1):
+        N, R = mpr.minplus_power(_dev(mpr, X), 6, sched)
+        Nr, Rr = O.power_chain(O.from_u16(X), 6)
+        assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
+        assert int(R[3].item()) == mpr.ROW_NONE
+
+
+def test_chain_full_size_rows_config2(mpr):
+    """N = 8192, 64-step chain (A^64), entries U[0,15] with 30% infinity:
+    sampled rows against the oracle's row-restricted chain."""
+    n, e = 8192, 64
+    X = synth.random_matrix(n, n, 3, 0, 15, 0.30)
+    N, R = mpr.minplus_power(_dev(mpr, X), e, mpr.CHAIN, check=True)
+    rows = [0, 4097, n - 1]
+    Nr, Rr = O.chain_rows(O.from_u16(X), rows, e)
+    assert np.array_equal(_host(N)[rows], _u16(Nr))
+    assert np.array_equal(R.cpu().numpy()[rows], Rr)
+
+
+# ------------------------------------------------------------------ traces
+def test_traces(mpr):
+    A = O.transfer(5)
+    Pa, Pb = O.power_chain(A, 6), O.power_chain(A, 9)
+    Xd, Yd = _dev(mpr, _u16(Pa[0])), _dev(mpr, _u16(Pb[0]))
+    RX, RY = torch.from_numpy(Pa[1]).cuda(), torch.from_numpy(Pb[1]).cuda()
+    assert int(mpr.trace_min(Xd, RX).item()) == O.trace(*Pa)
+    g = int(mpr.trace_of_product(Xd, RX, Yd, RY).item())
+    assert g == O.trace(*O.product_of_powers(*Pa, *Pb)) == O.gamma(5, 15)
+    # ragged size, random offsets, empty row
+    n = 203
+    X = synth.random_matrix(n, n, 21, 0, 30, 0.4)
+    Y = synth.random_matrix(n, n, 22, 0, 30, 0.4)
+    rx = (np.arange(n) * 7 % 13).astype(np.int64)
+    ry = (np.arange(n) * 5 % 11).astype(np.int64)
+    rx[4] = O.INF
+    X[4, :] = 0xFFFF
+    ref = O.trace(*O.product_of_powers(O.from_u16(X), rx, O.from_u16(Y), ry))
+    got = int(mpr.trace_of_product(_dev(mpr, X), torch.from_numpy(rx).cuda(), _dev(mpr, Y),
+                                   torch.from_numpy(ry).cuda()).item())
+    assert got == ref
+
+
+# ------------------------------------------------------------------ gamma_R and periods
+def test_config1_gamma_m3(mpr):
+    """P_3 x C_n for n = 3..40 from one GPU chain, vs oracle and brute force."""
+    A = mpr.build_transfer(3)
+    mu, lam, c, tr = mpr.find_period(A, 40, traces=True)
+    assert (mu, lam, c) == (11, 4, 6)
+    for n in range(3, 41):
+        assert tr[n] == O.gamma(3, n), n
+    for n in range(3, 6):
+        assert tr[n] == O.brute_gamma(3, n)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+def test_find_period_small_m(mpr, m):
+    A = mpr.build_transfer(m)
+    mu, lam, c, tr = mpr.find_period(A, 60, traces=True)
+    omu, olam, oc, og = O.find_period(O.transfer(m), 60)
+    assert (mu, lam, c) == (omu, olam, oc)
+    for k in range(1, 61):
+        ref = O.gamma_from_period(k, omu, olam, oc, og) if k > max(og) else og[k]
+        assert tr[k] == ref, k
+
+
+def test_find_period_stops_early_without_traces(mpr):
+    A = mpr.build_transfer(5)
+    mu, lam, c, tr = mpr.find_period(A, 300, traces=False)
+    assert (mu, lam, c) == (16, 5, 12) and tr is None
+
+
+def test_find_period_not_found(mpr):
+    A = mpr.build_transfer(6)
+    mu, lam, c, tr = mpr.find_period(A, 10, traces=True)
+    assert mu is None
+    assert tr[10] == O.gamma(6, 10)
