@@ -247,6 +247,58 @@ mpr_status mpr_graph_launch(void *graph, mpr_stream stream);
 mpr_status mpr_graph_destroy(void *graph);
 
 /* ------------------------------------------------------------------ */
+/* Query server: continuous batching of gamma_R(P_m x C_n) requests.   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int device;               /* HIP device the engine runs on */
+    int baby;                 /* B: baby steps A^1..A^B, giant steps A^(B i) */
+    int64_t max_n;            /* largest n served (n >= 3) */
+    int max_batch;            /* most queries in one grouped launch */
+    int slots;                /* grouped launches in flight (1..64) */
+    size_t hbm_budget_bytes;  /* ladders are admitted only within this */
+} mpr_server_options;
+
+typedef struct {
+    int64_t tag;              /* the caller's tag from mpr_server_submit */
+    int m;
+    int64_t n;
+    int64_t gamma;            /* gamma_R(P_m x C_n) when status == MPR_OK */
+    int status;
+    int cold;                 /* 1 when the request waited for a ladder build */
+    double t_submit_s, t_start_s, t_done_s; /* server clock (mpr_server_now) */
+} mpr_query_result;
+
+typedef struct {
+    int64_t submitted, completed, batches, max_batch_seen;
+    int64_t builds, evictions, admission_waits, resident_bytes;
+} mpr_server_stats;
+
+/* Starts an engine with its own worker thread and two non-blocking HIP
+ * streams (queries, ladder builds).  For each m it keeps the canonical
+ * powers A^1..A^B and A^(B i), i <= (max_n - 1) / B, resident, and answers
+ * n = B i + j (1 <= j <= B) as the trace of A^(B i) (x) A^j (Corollary 7)
+ * without forming the product.  The engine allocates its ladders itself,
+ * within hbm_budget_bytes (least recently used idle ladders are evicted;
+ * requests that do not fit wait).  *server_host receives an opaque handle. */
+mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host);
+/* Queues gamma_R(P_m x C_n); non-blocking and thread-safe.  Requests with
+ * m outside 1..11 or n outside 3..max_n complete with MPR_EINVAL. */
+mpr_status mpr_server_submit(void *server, int m, int64_t n, int64_t tag);
+/* Moves up to capacity finished requests into out_host (host array),
+ * waiting up to wait_ms for the first one.  *count_host = number moved. */
+mpr_status mpr_server_poll(void *server, mpr_query_result *out_host, int capacity, int *count_host,
+                           int wait_ms);
+/* Counters of the engine (host struct). */
+mpr_status mpr_server_stats_get(void *server, mpr_server_stats *out_host);
+/* Seconds since the engine started, on the clock of the result times. */
+double mpr_server_now(void *server);
+/* Device bytes one ladder of m takes for the given baby step and max_n. */
+int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n);
+/* Stops the worker, waits for outstanding GPU work, frees everything. */
+mpr_status mpr_server_destroy(void *server);
+
+/* ------------------------------------------------------------------ */
 /* Tile configurations and the autotuner's table.                      */
 /* ------------------------------------------------------------------ */
 

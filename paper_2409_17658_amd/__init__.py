@@ -46,6 +46,22 @@ class ChainDesc(ctypes.Structure):
                 ("R_out", ctypes.c_void_p)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("baby", ctypes.c_int), ("max_n", ctypes.c_int64),
+                ("max_batch", ctypes.c_int), ("slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("m", ctypes.c_int), ("n", ctypes.c_int64), ("gamma", ctypes.c_int64),
+                ("status", ctypes.c_int), ("cold", ctypes.c_int), ("t_submit_s", ctypes.c_double),
+                ("t_start_s", ctypes.c_double), ("t_done_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "batches", "max_batch_seen", "builds",
+                                             "evictions", "admission_waits", "resident_bytes")]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -81,6 +97,13 @@ _SIGS = {
     "mpr_batch_graph_create": (_I, [_P, _P, _P, _P]),
     "mpr_graph_launch": (_I, [_P, _P]),
     "mpr_graph_destroy": (_I, [_P]),
+    "mpr_server_create": (_I, [_P, _P]),
+    "mpr_server_submit": (_I, [_P, _I, _I64, _I64]),
+    "mpr_server_poll": (_I, [_P, _P, _I, _P, _I]),
+    "mpr_server_stats_get": (_I, [_P, _P]),
+    "mpr_server_now": (ctypes.c_double, [_P]),
+    "mpr_server_ladder_bytes": (_I64, [_I, _I, _I64]),
+    "mpr_server_destroy": (_I, [_P]),
     "mpr_gemm_config_count": (_I, []),
     "mpr_gemm_config_info": (_I, [_I, _P, _P, _P, _P, _P, _P]),
     "mpr_set_tile_table": (_I, [_P, _P, _I]),

@@ -1,0 +1,551 @@
+// serve.hip -- a continuous-batching query engine for gamma_R(P_m x C_n).
+//
+// For each m the engine keeps a "ladder" of canonical powers resident in
+// HBM: baby steps A^1 .. A^B (a chain) and giant steps A^B, A^2B, ..., and
+// answers n = B*i + j (1 <= j <= B) as the trace of A^(B i) (x) A^j, i.e.
+// one HBM-bound trace-of-product pass per query (Corollary 7; the product
+// is never formed).  n <= B is read off the baby traces computed once at
+// build time.
+//
+// A worker thread owns every HIP call.  Each tick it gathers the requests
+// whose ladder is ready into ONE grouped launch on the query stream (up to
+// kSlots launches in flight), while ladder builds run on a separate build
+// stream, so queries for warm m keep flowing while a cold m is built.  A
+// ladder is admitted only if its bytes fit the HBM budget; idle ladders are
+// evicted least-recently-used to make room, and requests that do not fit
+// wait in an admission queue.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <map>
+#include <string>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+namespace mpr {
+
+mpr_status transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s);
+int64_t transfer_size(int m);
+
+// ------------------------------------------------------------ grouped trace-of-product
+struct TPDesc {
+    const u16 *X;
+    const int64_t *RX;
+    const u16 *Y;
+    const int64_t *RY;
+    int64_t n, ld, tiles, first_block;
+};
+
+constexpr int GT = 64;
+
+__global__ __launch_bounds__(256) void grouped_trace_product_kernel(const TPDesc *__restrict__ d, int nq,
+                                                                    int64_t *out)
+{
+    __shared__ u16 yt[GT][GT + 2];
+    __shared__ int64_t sh[4];
+    __shared__ int qsel;
+    const int64_t b = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = nq - 1;  // last q with first_block <= b
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (d[mid].first_block <= b)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        qsel = lo;
+    }
+    __syncthreads();
+    const TPDesc q = d[qsel];
+    const int64_t t = b - q.first_block;
+    const int64_t i0 = (t / q.tiles) * GT, l0 = (t % q.tiles) * GT;
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+        const int r = e / GT, c = e % GT;
+        const int64_t l = l0 + r, i = i0 + c;
+        yt[c][r] = (l < q.n && i < q.n) ? q.Y[l * q.ld + i] : (u16)0xFFFF;
+    }
+    __syncthreads();
+    int64_t best = ROW_NONE;
+    for (int e = threadIdx.x; e < GT * GT; e += 256) {
+        const int r = e / GT, c = e % GT;
+        const int64_t i = i0 + r, l = l0 + c;
+        if (i >= q.n || l >= q.n) continue;
+        const uint32_t x = q.X[i * q.ld + l], y = yt[r][c];
+        if (x == 0xFFFFu || y == 0xFFFFu) continue;
+        const int64_t rx = q.RX[i], ry = q.RY[l];
+        if (rx == ROW_NONE || ry == ROW_NONE) continue;
+        const int64_t v = rx + ry + (int64_t)(x + y);
+        best = v < best ? v : best;
+    }
+    best = wave_min_i64(best);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t v = sh[0];
+        for (int w = 1; w < 4; w++) v = sh[w] < v ? sh[w] : v;
+        if (v != ROW_NONE) atomicMin((long long *)&out[qsel], (long long)v);
+    }
+}
+
+__global__ void fill_none_kernel(int64_t *p, int count)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = ROW_NONE;
+}
+
+// ------------------------------------------------------------ engine
+using Clock = std::chrono::steady_clock;
+
+struct Ladder {
+    int m = 0;
+    int64_t n = 0, ld = 0;
+    enum State { NONE, BUILDING, READY, FAILED } state = NONE;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    std::vector<u16 *> Nb, Ng;        // baby[1..B], giant[1..G] (giant[1] = baby[B])
+    std::vector<int64_t *> Rb, Rg;
+    std::vector<int64_t> baby_trace;  // host, index j = 1..B
+    hipEvent_t ready = nullptr;
+    int64_t *trace_dev = nullptr;
+    int32_t *status_dev = nullptr;
+    int inflight = 0;
+    double last_use = 0;
+    double build_s0 = 0, build_s = 0;
+};
+
+struct Request {
+    int64_t tag;
+    int m;
+    int64_t n;
+    double t_submit;
+    bool cold = false;
+};
+
+struct Slot {
+    bool busy = false;
+    hipEvent_t done = nullptr;
+    TPDesc *desc_host = nullptr;  // pinned
+    TPDesc *desc_dev = nullptr;
+    int64_t *out_dev = nullptr;
+    int64_t *out_host = nullptr;  // pinned
+    std::vector<Request> reqs;
+    double t_launch = 0;
+};
+
+struct Server {
+    mpr_server_options opt;
+    int device = 0;
+    hipStream_t qstream = nullptr, bstream = nullptr;
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_in, cv_out;
+    std::deque<Request> inbox;
+    std::deque<mpr_query_result> outbox;
+    bool stop = false;
+    std::thread worker;
+    // worker-owned
+    std::map<int, Ladder> ladders;
+    std::map<int, std::deque<Request>> waiting;  // per m, ladder not ready
+    std::deque<int> admission;                   // m values waiting for memory
+    std::vector<Slot> slots;
+    size_t resident = 0;
+    mpr_server_stats stats;
+    std::string fatal;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+static size_t ladder_bytes(int m, int B, int G, int64_t *n_out, int64_t *ld_out)
+{
+    const int64_t n = transfer_size(m), ld = round_up(n, 8);
+    const size_t mat = (size_t)round_up(n * ld * 2, 256), vec = (size_t)round_up(n * 8, 256);
+    // A, B babies, G-1 further giants, one folded operand; then the scalars
+    const size_t count = 1 + (size_t)B + (size_t)(G > 1 ? G - 1 : 0) + 1;
+    if (n_out) *n_out = n;
+    if (ld_out) *ld_out = ld;
+    return count * (mat + vec) + (size_t)round_up((int64_t)(B + 8) * 8, 256);
+}
+
+static int giant_count(const mpr_server_options &o) { return (int)((o.max_n - 1) / o.baby); }
+
+// Enqueues the whole ladder build on the build stream.
+static mpr_status start_build(Server &S, Ladder &L)
+{
+    const int B = S.opt.baby, G = giant_count(S.opt);
+    L.bytes = ladder_bytes(L.m, B, G, &L.n, &L.ld);
+    if (hipMalloc(&L.mem, L.bytes) != hipSuccess) return MPR_ENOMEM;
+    const int64_t n = L.n, ld = L.ld;
+    const size_t mat = (size_t)round_up(n * ld * 2, 256), vec = (size_t)round_up(n * 8, 256);
+    char *p = (char *)L.mem;
+    auto take_mat = [&]() { u16 *r = (u16 *)p; p += mat; return r; };
+    auto take_vec = [&]() { int64_t *r = (int64_t *)p; p += vec; return r; };
+    u16 *A = take_mat();
+    (void)take_vec();
+    L.Nb.assign(B + 1, nullptr);
+    L.Rb.assign(B + 1, nullptr);
+    for (int j = 1; j <= B; j++) {
+        L.Nb[j] = take_mat();
+        L.Rb[j] = take_vec();
+    }
+    L.Ng.assign(G + 1, nullptr);
+    L.Rg.assign(G + 1, nullptr);
+    if (G >= 1) {
+        L.Ng[1] = L.Nb[B];
+        L.Rg[1] = L.Rb[B];
+    }
+    for (int i = 2; i <= G; i++) {
+        L.Ng[i] = take_mat();
+        L.Rg[i] = take_vec();
+    }
+    u16 *Bp = take_mat();
+    (void)take_vec();
+    int64_t *scal = (int64_t *)p;  // [0] s of the fold, [1..B] traces, then the status word
+    L.trace_dev = scal + 1;
+    L.status_dev = (int32_t *)(scal + 2 + B);
+    hipStream_t s = S.bstream;
+    mpr_status e = fill_i32_launch(L.status_dev, 1, 0, s);
+    if (e == MPR_OK) e = transfer_launch(L.m, A, ld, s);
+    if (e == MPR_OK) e = copy_launch(A, ld, L.Nb[1], ld, n, n, s);
+    if (e == MPR_OK) e = normalise_launch(n, n, L.Nb[1], ld, nullptr, nullptr, L.Rb[1], L.status_dev, nullptr, s);
+    for (int j = 2; j <= B && e == MPR_OK; j++) {
+        e = gemm_launch(-1, n, n, n, L.Nb[j - 1], ld, A, ld, L.Nb[j], ld, s);
+        if (e == MPR_OK)
+            e = normalise_launch(n, n, L.Nb[j], ld, L.Rb[j - 1], nullptr, L.Rb[j], L.status_dev, nullptr, s);
+    }
+    for (int j = 1; j <= B && e == MPR_OK; j++) e = trace_launch(L.Nb[j], n, ld, L.Rb[j], L.trace_dev + (j - 1), s);
+    if (G >= 2 && e == MPR_OK) e = fold_launch(L.Ng[1], ld, L.Rg[1], n, n, Bp, ld, scal, L.status_dev, s);
+    for (int i = 2; i <= G && e == MPR_OK; i++) {
+        e = gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, Bp, ld, L.Ng[i], ld, s);
+        if (e == MPR_OK)
+            e = normalise_launch(n, n, L.Ng[i], ld, L.Rg[i - 1], scal, L.Rg[i], L.status_dev, nullptr, s);
+    }
+    if (e != MPR_OK) return e;
+    if (hipEventCreateWithFlags(&L.ready, hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
+    if (hipEventRecord(L.ready, s) != hipSuccess) return MPR_EHIP;
+    L.state = Ladder::BUILDING;
+    L.build_s0 = S.now();
+    S.resident += L.bytes;
+    S.stats.builds++;
+    return MPR_OK;
+}
+
+static void free_ladder(Server &S, Ladder &L)
+{
+    if (L.ready) (void)hipEventDestroy(L.ready);
+    if (L.mem) (void)hipFree(L.mem);
+    S.resident -= L.bytes;
+    L = Ladder();
+}
+
+static void complete(Server &S, const Request &r, int64_t gamma, int status, double t_start)
+{
+    mpr_query_result q;
+    q.tag = r.tag;
+    q.m = r.m;
+    q.n = r.n;
+    q.gamma = gamma;
+    q.status = status;
+    q.t_submit_s = r.t_submit;
+    q.t_start_s = t_start;
+    q.t_done_s = S.now();
+    q.cold = r.cold ? 1 : 0;
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.outbox.push_back(q);
+    S.stats.completed++;
+    S.cv_out.notify_all();
+}
+
+// Try to admit ladder m; evicts idle ladders LRU.  True when building.
+static bool admit(Server &S, int m)
+{
+    const int B = S.opt.baby, G = giant_count(S.opt);
+    const size_t need = ladder_bytes(m, B, G, nullptr, nullptr);
+    if (need > S.opt.hbm_budget_bytes) return false;
+    while (S.resident + need > S.opt.hbm_budget_bytes) {
+        Ladder *victim = nullptr;
+        for (auto &kv : S.ladders) {
+            Ladder &L = kv.second;
+            if (L.state != Ladder::READY || L.inflight > 0 || !S.waiting[kv.first].empty()) continue;
+            if (!victim || L.last_use < victim->last_use) victim = &L;
+        }
+        if (!victim) return false;
+        free_ladder(S, *victim);
+        S.stats.evictions++;
+    }
+    Ladder &L = S.ladders[m];
+    L.m = m;
+    if (start_build(S, L) != MPR_OK) {
+        if (L.mem) free_ladder(S, L);
+        L.state = Ladder::FAILED;
+        return true;  // the failure is reported to the waiting requests
+    }
+    return true;
+}
+
+static void worker_main(Server *Sp)
+{
+    Server &S = *Sp;
+    (void)hipSetDevice(S.device);
+    const int B = S.opt.baby;
+    for (;;) {
+        std::vector<Request> fresh;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            bool busy = !S.admission.empty();
+            for (auto &sl : S.slots) busy |= sl.busy;
+            for (auto &kv : S.ladders) busy |= kv.second.state == Ladder::BUILDING;
+            if (S.inbox.empty() && !S.stop) S.cv_in.wait_for(lk, std::chrono::microseconds(busy ? 50 : 2000));
+            if (S.stop) break;
+            while (!S.inbox.empty()) {
+                fresh.push_back(S.inbox.front());
+                S.inbox.pop_front();
+            }
+        }
+        // 1. retire finished batches
+        for (auto &sl : S.slots) {
+            if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
+            for (size_t q = 0; q < sl.reqs.size(); q++) {
+                const Request &r = sl.reqs[q];
+                Ladder &L = S.ladders[r.m];
+                L.inflight--;
+                complete(S, r, sl.out_host[q], MPR_OK, sl.t_launch);
+            }
+            sl.reqs.clear();
+            sl.busy = false;
+        }
+        // 2. builds that finished
+        for (auto &kv : S.ladders) {
+            Ladder &L = kv.second;
+            if (L.state != Ladder::BUILDING || hipEventQuery(L.ready) != hipSuccess) continue;
+            int32_t st = 0;
+            L.baby_trace.assign(B + 1, ROW_NONE);
+            if (hipMemcpy(&st, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                st = MPR_EHIP;
+            L.state = st == 0 ? Ladder::READY : Ladder::FAILED;
+            L.build_s = S.now() - L.build_s0;
+            L.last_use = S.now();
+        }
+        // 3. route new requests
+        for (auto &r : fresh) {
+            if (r.m < 1 || r.m > 11 || r.n < 3 || r.n > S.opt.max_n) {
+                complete(S, r, ROW_NONE, MPR_EINVAL, S.now());
+                continue;
+            }
+            auto it = S.ladders.find(r.m);
+            if (it == S.ladders.end() || it->second.state == Ladder::NONE) {
+                r.cold = true;
+                bool queued = std::find(S.admission.begin(), S.admission.end(), r.m) != S.admission.end();
+                if (!queued && !admit(S, r.m)) {
+                    S.admission.push_back(r.m);
+                    S.stats.admission_waits++;
+                }
+            } else if (it->second.state == Ladder::BUILDING) {
+                r.cold = true;
+            }
+            S.waiting[r.m].push_back(r);
+        }
+        // 4. admission queue (memory may have been released)
+        for (size_t k = 0; k < S.admission.size();) {
+            const int m = S.admission[k];
+            if (admit(S, m))
+                S.admission.erase(S.admission.begin() + k);
+            else
+                k++;
+        }
+        // 5. one grouped launch for everything that is ready
+        Slot *slot = nullptr;
+        for (auto &sl : S.slots)
+            if (!sl.busy) {
+                slot = &sl;
+                break;
+            }
+        std::vector<Request> batch;
+        for (auto &kv : S.waiting) {
+            Ladder &L = S.ladders[kv.first];
+            if (L.state == Ladder::FAILED) {
+                for (auto &r : kv.second) complete(S, r, ROW_NONE, MPR_EOVERFLOW, S.now());
+                kv.second.clear();
+                continue;
+            }
+            if (L.state != Ladder::READY) continue;
+            auto &dq = kv.second;
+            while (!dq.empty()) {
+                Request r = dq.front();
+                const int64_t i = (r.n - 1) / B, j = r.n - B * i;
+                if (i == 0) {  // read off the build's trace of A^j
+                    dq.pop_front();
+                    L.last_use = S.now();
+                    complete(S, r, L.baby_trace[j], MPR_OK, S.now());
+                    continue;
+                }
+                if (!slot || (int)batch.size() >= S.opt.max_batch) break;
+                dq.pop_front();
+                batch.push_back(r);
+            }
+        }
+        if (slot && !batch.empty()) {
+            int64_t blocks = 0;
+            for (size_t q = 0; q < batch.size(); q++) {
+                const Request &r = batch[q];
+                Ladder &L = S.ladders[r.m];
+                const int64_t i = (r.n - 1) / B, j = r.n - B * i;
+                const int64_t tiles = (L.n + GT - 1) / GT;
+                slot->desc_host[q] = TPDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, tiles, blocks};
+                blocks += tiles * tiles;
+                L.inflight++;
+                L.last_use = S.now();
+            }
+            const int nq = (int)batch.size();
+            hipStream_t s = S.qstream;
+            bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TPDesc) * nq, hipMemcpyHostToDevice,
+                                     s) == hipSuccess;
+            hipLaunchKernelGGL(fill_none_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, slot->out_dev, nq);
+            hipLaunchKernelGGL(grouped_trace_product_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
+                               nq, slot->out_dev);
+            ok = ok && hipGetLastError() == hipSuccess;
+            ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * nq, hipMemcpyDeviceToHost, s) == hipSuccess;
+            ok = ok && hipEventRecord(slot->done, s) == hipSuccess;
+            if (!ok) {
+                S.fatal = "launch failed";
+                for (auto &r : batch) {
+                    S.ladders[r.m].inflight--;
+                    complete(S, r, ROW_NONE, MPR_EHIP, S.now());
+                }
+                continue;
+            }
+            slot->reqs = batch;
+            slot->busy = true;
+            slot->t_launch = S.now();
+            S.stats.batches++;
+            S.stats.max_batch_seen = std::max<int64_t>(S.stats.max_batch_seen, nq);
+        }
+        S.stats.resident_bytes = (int64_t)S.resident;
+    }
+}
+
+}  // namespace mpr
+
+using namespace mpr;
+
+extern "C" mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host)
+{
+    if (!opt || !server_host) return MPR_EINVAL;
+    if (opt->baby < 1 || opt->max_n < 3 || opt->max_batch < 1 || opt->slots < 1 || opt->slots > 64)
+        return MPR_EINVAL;
+    if (hipSetDevice(opt->device) != hipSuccess) return MPR_EUNSUPPORTED;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    Server *S = new Server();
+    S->opt = *opt;
+    S->device = opt->device;
+    memset(&S->stats, 0, sizeof(S->stats));
+    S->t0 = Clock::now();
+    bool ok = hipStreamCreateWithFlags(&S->qstream, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&S->bstream, hipStreamNonBlocking) == hipSuccess;
+    S->slots.resize(opt->slots);
+    for (auto &sl : S->slots) {
+        ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&sl.desc_host, sizeof(TPDesc) * opt->max_batch) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&sl.out_host, 8 * opt->max_batch) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.desc_dev, sizeof(TPDesc) * opt->max_batch) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.out_dev, 8 * opt->max_batch) == hipSuccess;
+    }
+    if (!ok) {
+        mpr_server_destroy(S);
+        return MPR_EHIP;
+    }
+    S->worker = std::thread(worker_main, S);
+    *server_host = S;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_server_submit(void *server, int m, int64_t n, int64_t tag)
+{
+    Server *S = (Server *)server;
+    if (!S) return MPR_EINVAL;
+    Request r;
+    r.tag = tag;
+    r.m = m;
+    r.n = n;
+    r.t_submit = S->now();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->inbox.push_back(r);
+        S->stats.submitted++;
+    }
+    S->cv_in.notify_one();
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_server_poll(void *server, mpr_query_result *out_host, int capacity, int *count_host,
+                                      int wait_ms)
+{
+    Server *S = (Server *)server;
+    if (!S || !out_host || !count_host || capacity < 1) return MPR_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->outbox.empty() && wait_ms > 0) S->cv_out.wait_for(lk, std::chrono::milliseconds(wait_ms));
+    int c = 0;
+    while (c < capacity && !S->outbox.empty()) {
+        out_host[c++] = S->outbox.front();
+        S->outbox.pop_front();
+    }
+    *count_host = c;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_server_stats_get(void *server, mpr_server_stats *out_host)
+{
+    Server *S = (Server *)server;
+    if (!S || !out_host) return MPR_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out_host = S->stats;
+    return MPR_OK;
+}
+
+extern "C" double mpr_server_now(void *server)
+{
+    Server *S = (Server *)server;
+    return S ? S->now() : 0.0;
+}
+
+extern "C" int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n)
+{
+    if (m < 1 || m > 11 || baby < 1 || max_n < 3) return -1;
+    return (int64_t)ladder_bytes(m, baby, (int)((max_n - 1) / baby), nullptr, nullptr);
+}
+
+extern "C" mpr_status mpr_server_destroy(void *server)
+{
+    Server *S = (Server *)server;
+    if (!S) return MPR_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_in.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    if (S->qstream) (void)hipStreamSynchronize(S->qstream);
+    if (S->bstream) (void)hipStreamSynchronize(S->bstream);
+    for (auto &kv : S->ladders)
+        if (kv.second.mem) free_ladder(*S, kv.second);
+    for (auto &sl : S->slots) {
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.desc_host) (void)hipHostFree(sl.desc_host);
+        if (sl.out_host) (void)hipHostFree(sl.out_host);
+        if (sl.desc_dev) (void)hipFree(sl.desc_dev);
+        if (sl.out_dev) (void)hipFree(sl.out_dev);
+    }
+    if (S->qstream) (void)hipStreamDestroy(S->qstream);
+    if (S->bstream) (void)hipStreamDestroy(S->bstream);
+    delete S;
+    return MPR_OK;
+}

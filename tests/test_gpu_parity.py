@@ -74,9 +74,9 @@ def test_gemm_extremes(mpr):
     n = 70
     X = synth.random_matrix(n, n, 3, 0, 0x7FFF, 0.3)
     Y = synth.random_matrix(n, n, 4, 0x7000, 0x7FFF, 0.2)
+    X[:, 0] = 0x7FFF
     X[5, :] = 0xFFFF
     Y[:, 9] = 0xFFFF
-    X[:, 0] = 0x7FFF
     ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
     C = mpr.minplus_gemm(_dev(mpr, X), _dev(mpr, Y))
     got = _host(C)

@@ -1,0 +1,57 @@
+"""Roman transfer matrices for m = 6, 7, 8 (the paper's new cases): powers
+to n = 300 by the chain and by binary powering, the least period, and
+gamma_R for n = 3..300, against the stored oracle goldens (bit-exact
+canonical-form digests at selected k)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load(m):
+    with open(os.path.join(HERE, "roman_m%d.json" % m)) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def mpr():
+    import paper_2409_17658_amd as m
+
+    m.lib()
+    m.init(0)
+    return m
+
+
+def digest(N, R):
+    n = N.shape[0]
+    h = np.ascontiguousarray(N.cpu().numpy()[:, :n]).astype("<u2").tobytes()
+    return hashlib.sha256(h + np.ascontiguousarray(R.cpu().numpy(), dtype="<i8").tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("m", [6, 7, 8])
+def test_period_and_gamma_to_300(mpr, m):
+    print("roman m", m, flush=True)
+    g = load(m)
+    A = mpr.build_transfer(m)
+    mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=40)
+    assert [mu, lam, c] == g["period"]
+    for k in range(1, 301):
+        assert tr[k] == g["trace"][str(k)], k
+
+
+@pytest.mark.parametrize("m", [6, 7, 8])
+def test_chain_and_squaring_digests(mpr, m):
+    g = load(m)
+    A = mpr.build_transfer(m)
+    for k in (1, 2, 3, 21, 26, 64, 128, 299, 300):
+        for sched in (mpr.CHAIN, mpr.SQUARE):
+            if sched == mpr.CHAIN and k not in (1, 3, 26, 300):
+                continue
+            N, R = mpr.minplus_power(A, k, sched)
+            assert digest(N, R) == g["digest_sha256"][str(k)], (k, sched)

@@ -1,0 +1,65 @@
+"""The query server: answers equal the oracle's gamma_R, and every answer is
+the same when the query runs alone and when it runs inside a Poisson mix
+(tolerance 0); a tiny HBM budget forces admission waits and evictions."""
+import math
+
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def oracle_gamma(m, n):
+    if m not in _CACHE:
+        A = O.transfer(m)
+        _CACHE[m] = O.find_period(A, 60)
+    mu, lam, c, g = _CACHE[m]
+    return O.gamma_from_period(n, mu, lam, c, g)
+
+
+@pytest.fixture(scope="module")
+def serve():
+    import paper_2409_17658_amd as m
+    from paper_2409_17658_amd import serve as s
+
+    m.lib()
+    m.init(0)
+    return s
+
+
+def test_server_alone_and_in_mix(serve):
+    qs = synth.poisson_queries(400.0, 300, seed=5, m_range=(2, 6), n_range=(3, 200))
+    with serve.Server(baby=16, max_n=200, max_batch=64, slots=4, hbm_budget_bytes=8 << 30) as S:
+        mixed = serve.run_open_loop(S, qs, timeout_s=240)
+        st = S.stats()
+        alone = [S.query(m, n)["gamma"] for (_, m, n) in qs[:60]]
+    for (t, m, n), r in zip(qs, mixed):
+        assert r["status"] == 0
+        assert r["gamma"] == oracle_gamma(m, n), (m, n)
+    assert alone == [r["gamma"] for r in mixed[:60]]
+    assert st["completed"] == len(qs) and st["builds"] == 5
+    assert st["batches"] >= 1 and st["max_batch_seen"] >= 1
+
+
+def test_server_budget_forces_eviction(serve):
+    """Budget below two ladders: requests alternate between m = 5 and 6."""
+    b5, b6 = serve.ladder_bytes(5, 8, 64), serve.ladder_bytes(6, 8, 64)
+    with serve.Server(baby=8, max_n=64, max_batch=16, slots=2, hbm_budget_bytes=max(b5, b6) + 1024) as S:
+        out = [S.query(m, n) for m, n in [(5, 40), (6, 41), (5, 63), (6, 9), (5, 3)]]
+        st = S.stats()
+    for r in out:
+        assert r["status"] == 0 and r["gamma"] == oracle_gamma(r["m"], r["n"])
+    assert st["evictions"] >= 3 and st["builds"] >= 4
+
+
+def test_server_rejects_bad_queries(serve):
+    with serve.Server(baby=8, max_n=50, max_batch=8, slots=1, hbm_budget_bytes=1 << 30) as S:
+        assert S.query(3, 2)["status"] == 1
+        assert S.query(3, 51)["status"] == 1
+        assert S.query(0, 10)["status"] == 1
+        r = S.query(1, 50)
+        assert r["status"] == 0 and r["gamma"] == math.ceil(2 * 50 / 3)
