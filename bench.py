@@ -11,6 +11,10 @@ Prints ONE JSON line with the value, the roofline of the dominant kernel
 with HIP events on the launch stream) and the CPU oracle timed on a bounded
 sample of the same workload.
 
+The default run also drives the query server for --serve-seconds (a Poisson
+stream of gamma_R(P_m x C_n) requests at 200 req/s, m in 3..9, n in 3..1000,
+ladders pre-built) and adds its p50 / p99 latency under "serving".
+
 Other workloads (--workload config2|config3|config4|serve) print their own
 line in the same format.
 """
@@ -41,29 +45,31 @@ def valu_peak_gpairs(cus: int) -> float:
 
 def cpu_baseline_gemm(X, Y, target_s: float = 15.0):
     """The oracle (as it stands) on sampled full rows of the same product;
-    rate in the metric's unit (rows * N * N pairs / s)."""
+    rate in the metric's unit (rows * N * N pairs / s).  A first small
+    sample sizes the second one to about target_s seconds."""
     import oracle as O
 
     n = X.shape[0]
     Xi = O.from_u16(X)
     Yi = O.from_u16(Y)
     rng = np.random.default_rng(0)
-    rows = max(1, O.threads())
+    rows = max(2, 2 * O.threads())
     t0 = time.perf_counter()
     O.minplus(Xi[rng.integers(0, n, rows)], Yi)
     dt = time.perf_counter() - t0
-    done_rows, done_t = rows, dt
-    if dt < target_s / 3:
-        more = int(rows * (target_s - dt) / max(dt, 1e-3))
-        more = max(rows, min(more, 4096))
-        t0 = time.perf_counter()
-        O.minplus(Xi[rng.integers(0, n, more)], Yi)
-        dt2 = time.perf_counter() - t0
-        done_rows, done_t = more, dt2
-    rate = done_rows * n * n / done_t / 1e9
+    t0 = time.perf_counter()
+    O.minplus(Xi[rng.integers(0, n, 2 * rows)], Yi)
+    dt2 = time.perf_counter() - t0
+    per_row = max((dt2 - dt) / rows, 1e-4)  # marginal cost of a row
+    fixed = max(dt - rows * per_row, 0.0)   # per-call set-up (finite-entry lists)
+    more = int(max(rows, min(8192, (target_s - fixed) / per_row)))
+    t0 = time.perf_counter()
+    O.minplus(Xi[rng.integers(0, n, more)], Yi)
+    dt3 = time.perf_counter() - t0
+    rate = more * n * n / dt3 / 1e9
     return {"value": round(rate, 3), "unit": "G pairs/s", "cores": O.threads(), "kind": "oracle",
-            "sample": "%d random full rows of the N=%d product (%d x %d x %d pairs), %.1f s" %
-                      (done_rows, n, done_rows, n, n, done_t)}
+            "sample": "%d random full rows of the N=%d product (%d x %d x %d pairs counted), %.1f s" %
+                      (more, n, more, n, n, dt3)}
 
 
 def bench_gemm(args, mpr, torch):
@@ -119,10 +125,7 @@ def bench_gemm(args, mpr, torch):
     peak = valu_peak_gpairs(cus)
     kern_avg = float(np.mean(gemm_ms))
     achieved = pairs / (kern_avg * 1e-3) / 1e9
-    traffic = None
-    if args.traffic_json and os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+    traffic = load_traffic(args.traffic_json)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "G pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -141,6 +144,257 @@ def bench_gemm(args, mpr, torch):
     return out
 
 
+def kernel_source_digest() -> str:
+    """Digest of the sources the product kernel is built from (traffic
+    counters taken on another version are not reported)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("tile.h", "gemm.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2409_17658_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(path):
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(torch, nbytes=1 << 30):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters of a profiled run (FETCH_SIZE / WRITE_SIZE)."""
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return nbytes
+
+
+# ---------------------------------------------------------------- goldens
+def load_goldens():
+    """gamma_R tables stored by tests/golden/make_roman_golden.py (plain JSON)."""
+    gd = os.path.join(ROOT, "tests", "golden")
+    out = {}
+    for m in range(1, 9):
+        f = os.path.join(gd, "roman_m%d.json" % m)
+        if os.path.exists(f):
+            with open(f) as fh:
+                d = json.load(fh)
+            out[m] = ({int(k): v for k, v in d["trace"].items()}, tuple(d["period"]))
+    return out
+
+
+def expected_gamma(goldens, m, n):
+    """Stored table extended by the period (Proposition 8); m = 9 uses the
+    closed form of Section 4.3 (4n if 5 | n else 4n + 2)."""
+    if m == 9:
+        return 4 * n if n % 5 == 0 else 4 * n + 2
+    if m not in goldens:
+        return None
+    g, (mu, lam, c) = goldens[m]
+    if n in g:
+        return g[n]
+    q, r = divmod(n - mu, lam)
+    return g[mu + r] + c * q
+
+
+# ---------------------------------------------------------------- config 2
+def bench_config2(args, mpr, torch):
+    import synth
+
+    n, e = 8192, 64
+    X = synth.random_matrix(n, n, 3, 0, 15, 0.30)
+    A = mpr.to_device(X)
+    C = mpr.alloc_matrix(n, n)
+    ws = mpr.workspace(mpr.power_workspace_size(n, e, mpr.CHAIN))
+    N = mpr.alloc_matrix(n, n)
+    R = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mpr.minplus_gemm(A, A, C, check=False)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        mpr.minplus_gemm(A, A, C, check=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_single = float(np.median(ts))
+    mpr.minplus_power(A, 3, mpr.CHAIN, N, R, ws, check=False, d_status=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mpr.minplus_power(A, e, mpr.CHAIN, N, R, ws, check=False, d_status=st)
+    torch.cuda.synchronize()
+    t_chain = time.perf_counter() - t0
+    mpr.check_status(st)
+    pairs = float(n) ** 3
+    return {"metric": "min-plus GOPS, N=8192 single product and 64-power chain", "value": round(63 * pairs / t_chain / 1e9, 1),
+            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16",
+            "data": "synthetic (SplitMix64 seed 3; uniform [0,15], 30% infinity)",
+            "config": {"workload": "A^64 by the chain, N=8192, normalised every step", "n": n, "e": e},
+            "single_product_ms": round(t_single * 1e3, 3), "single_product_gpairs": round(pairs / t_single / 1e9, 1),
+            "chain_s": round(t_chain, 3)}
+
+
+# ---------------------------------------------------------------- config 3
+def bench_config3(args, mpr, torch):
+    goldens = load_goldens()
+    per_m = {}
+    for m in (6, 7, 8):
+        A = mpr.build_transfer(m)
+        n = A.shape[0]
+        ws = mpr.workspace(mpr.power_workspace_size(n, 300, mpr.SQUARE))
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        N = mpr.alloc_matrix(n, n)
+        R = torch.empty(n, dtype=torch.int64, device="cuda")
+        mpr.minplus_power(A, 4, mpr.CHAIN, N, R, ws, check=False, d_status=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mpr.minplus_power(A, 300, mpr.CHAIN, N, R, ws, check=False, d_status=st)
+        torch.cuda.synchronize()
+        t_chain = time.perf_counter() - t0
+        Nc = N.clone()
+        Rc = R.clone()
+        t0 = time.perf_counter()
+        mpr.minplus_power(A, 300, mpr.SQUARE, N, R, ws, check=False, d_status=st)
+        torch.cuda.synchronize()
+        t_sq = time.perf_counter() - t0
+        same = bool(torch.equal(Nc.view(torch.int16), N.view(torch.int16)) and torch.equal(Rc, R))
+        mpr.check_status(st)
+        t0 = time.perf_counter()
+        mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=40)
+        t_per = time.perf_counter() - t0
+        ok = None
+        if m in goldens:
+            g, per = goldens[m]
+            ok = (mu, lam, c) == per and all(int(tr[k]) == g[k] for k in range(1, 301))
+        per_m[m] = {"n_states": n, "period": [mu, lam, c], "chain_300_s": round(t_chain, 3),
+                    "chain_gpairs": round(299 * float(n) ** 3 / t_chain / 1e9, 1),
+                    "square_300_s": round(t_sq, 4), "chain_equals_square": same,
+                    "find_period_300_s": round(t_per, 3), "gamma_3_300_match_golden": ok}
+    tot = sum(299 * float(v["n_states"]) ** 3 for v in per_m.values())
+    tt = sum(v["chain_300_s"] for v in per_m.values())
+    return {"metric": "Roman transfer powers to n=300 (m=6,7,8): chain GOPS", "value": round(tot / tt / 1e9, 1),
+            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16", "data": "transfer matrices",
+            "config": {"workload": "A(G)^300 by chain and by squaring, period search, gamma_R(3..300)"},
+            "per_m": per_m}
+
+
+# ---------------------------------------------------------------- config 4
+def bench_config4(args, mpr, torch):
+    import synth
+
+    inst = synth.batch_instances(256, seed=4)
+    t_gen = time.perf_counter()
+    chains = []
+    for d in inst:
+        X = synth.random_matrix(d["n"], d["n"], d["seed"], 0, 31, 0.25)
+        A = mpr.to_device(X)
+        chains.append((A, d["e"], mpr.alloc_matrix(d["n"], d["n"]), torch.empty(d["n"], dtype=torch.int64, device="cuda")))
+    gen_s = time.perf_counter() - t_gen
+    pairs = sum((d["e"] - 1) * float(d["n"]) ** 3 for d in inst)
+    ws = mpr.workspace(mpr.batch_workspace_size(chains))
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    # autotune: time one launch per batched configuration
+    tune = {}
+    for cfg in range(mpr.batch_config_count()):
+        mpr.set_batch_config(cfg)
+        mpr.batch_plan(chains, ws, stream)
+        t0 = time.perf_counter()
+        mpr.batch_launch(ws, st, stream)
+        stream.synchronize()
+        tune[cfg] = time.perf_counter() - t0
+    best = min(tune, key=tune.get)
+    mpr.set_batch_config(best)
+    mpr.batch_plan(chains, ws, stream)
+    g = mpr.batch_graph_create(ws, st, stream)
+    mpr.graph_launch(g, stream)
+    stream.synchronize()
+    reps = max(1, args.batch_reps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mpr.graph_launch(g, stream)
+    stream.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    mpr.graph_destroy(g)
+    mpr.set_batch_config(-1)
+    mpr.check_status(st)
+    batched = [(N.clone(), R.clone()) for (_, _, N, R) in chains]
+    # the plain per-instance path: one chain after another
+    wsi = mpr.workspace(max(mpr.power_workspace_size(d["n"], d["e"], mpr.CHAIN) for d in inst))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (A, e, N, R) in chains:
+        mpr.minplus_power(A, e, mpr.CHAIN, N, R, wsi, check=False, d_status=st)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    mpr.check_status(st)
+    same = all(torch.equal(N.view(torch.int16), b[0].view(torch.int16)) and torch.equal(R, b[1])
+               for (_, _, N, R), b in zip(chains, batched))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return {"metric": "batched min-plus power chains GOPS (256 chains, one persistent launch in a HIP graph)",
+            "value": round(pairs / t_batch / 1e9, 1), "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "u16", "data": "synthetic (batch_instances seed 4; entries U[0,31], 25% infinity)",
+            "config": {"workload": "256 chains, N log-uniform [256,4096], e uniform [8,128]",
+                       "total_pairs": pairs, "batch_config": best,
+                       "panel_rows": mpr.batch_config_info(best)["panel_rows"]},
+            "batched_s": round(t_batch, 3), "per_instance_s": round(t_solo, 3),
+            "per_instance_gpairs": round(pairs / t_solo / 1e9, 1),
+            "speedup_vs_per_instance": round(t_solo / t_batch, 2),
+            "pct_valu_peak": round(100 * pairs / t_batch / 1e9 / valu_peak_gpairs(cus), 2),
+            "autotune_s": {str(k): round(v, 3) for k, v in tune.items()},
+            "batched_equals_per_instance": bool(same), "input_gen_s": round(gen_s, 1)}
+
+
+# ---------------------------------------------------------------- config 5
+def bench_serve(args, mpr, torch, seconds: float):
+    import synth
+    from paper_2409_17658_amd import serve
+
+    goldens = load_goldens()
+    rate = 200.0
+    qs = synth.poisson_queries(rate, int(rate * seconds), seed=5, m_range=(3, 9), n_range=(3, 1000))
+    budget = int(args.serve_budget_gb * (1 << 30))
+    out = {}
+    with serve.Server(baby=32, max_n=1000, max_batch=256, slots=4, hbm_budget_bytes=budget) as S:
+        build_s = {}
+        if args.serve_prewarm:
+            for m in range(3, 10):
+                t0 = time.perf_counter()
+                r = S.query(m, 1000)
+                build_s[m] = round(time.perf_counter() - t0, 3)
+                assert r["status"] == 0
+        t0 = time.perf_counter()
+        res = serve.run_open_loop(S, qs, timeout_s=seconds * 4 + 600)
+        wall = time.perf_counter() - t0
+        stats = S.stats()
+    lat = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in res])
+    cold = np.array([r["cold"] == 1 for r in res])
+    bad = sum(1 for r in res if r["status"] != 0)
+    checked = wrong = 0
+    for (t, m, n), r in zip(qs, res):
+        exp = expected_gamma(goldens, m, n)
+        if exp is not None:
+            checked += 1
+            wrong += int(r["gamma"] != exp)
+    out = {"queries": len(qs), "offered_qps": rate, "achieved_qps": round(len(qs) / wall, 1),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "warm_p50_ms": round(float(np.percentile(lat[~cold], 50)), 3) if (~cold).any() else None,
+           "warm_p99_ms": round(float(np.percentile(lat[~cold], 99)), 3) if (~cold).any() else None,
+           "cold_queries": int(cold.sum()),
+           "cold_p99_ms": round(float(np.percentile(lat[cold], 99)), 3) if cold.any() else None,
+           "prewarm_build_s": build_s, "errors": bad, "checked": checked, "mismatches": wrong,
+           "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
+           "resident_gb": round(stats["resident_bytes"] / (1 << 30), 2), "evictions": stats["evictions"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,9 +402,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--cfg", type=int, default=-1, help="tile configuration (-1: tile table)")
-    ap.add_argument("--workload", default="gemm", choices=["gemm"])
+    ap.add_argument("--workload", default="gemm", choices=["gemm", "config2", "config3", "config4", "serve"])
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the Poisson query stream in the default run (0: none)")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-prewarm", type=int, default=1)
+    ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (scale for the HBM byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "gemm_traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,7 +424,23 @@ def main():
 
     torch.cuda.set_device(0)
     mpr.init(0)
-    out = bench_gemm(args, mpr, torch)
+    if args.copy_calibration:
+        copy_calibration(torch)
+    if args.workload == "gemm":
+        out = bench_gemm(args, mpr, torch)
+        if args.serve_seconds > 0:
+            out["serving"] = bench_serve(args, mpr, torch, args.serve_seconds)
+    elif args.workload == "config2":
+        out = bench_config2(args, mpr, torch)
+    elif args.workload == "config3":
+        out = bench_config3(args, mpr, torch)
+    elif args.workload == "config4":
+        out = bench_config4(args, mpr, torch)
+    else:
+        out = {"metric": "gamma_R query serving, Poisson 200 req/s, m in 3..9, n in 3..1000",
+               "unit": "ms", "n_gpus": 1, "higher_is_better": False}
+        out["serving"] = bench_serve(args, mpr, torch, args.serve_seconds if args.serve_seconds > 0 else 60.0)
+        out["value"] = out["serving"]["p99_ms"]
     print(json.dumps(out), flush=True)
 
 

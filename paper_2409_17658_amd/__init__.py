@@ -199,8 +199,14 @@ def version() -> int:
     return lib().mpr_version()
 
 
-def init(device: int = 0):
+def init(device: int = 0, tile_table: bool = True):
+    """Checks the device and installs the autotuner's persisted tile table
+    (tile_table.json next to the library) when there is one."""
     _ok(lib().mpr_init(device), "mpr_init")
+    if tile_table:
+        from .autotune import load_table
+
+        load_table()
 
 
 def transfer_size(m: int) -> int:

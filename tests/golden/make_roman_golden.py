@@ -5,7 +5,7 @@ k = 1..KMAX (gamma_R(P_m x C_n) for n >= 3, Corollary 7) and SHA-256 digests
 of the canonical form (N_k as little-endian uint16 row-major with 0xFFFF for
 infinity, followed by R_k as little-endian int64) at selected k.
 
-Usage: python tests/golden/make_roman_golden.py [m ...]   (default 6 7 8)
+Usage: python tests/golden/make_roman_golden.py [m ...]   (default 1..8)
 m = 8 takes several minutes on 8 cores.
 """
 import hashlib
@@ -59,4 +59,4 @@ def main(ms):
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [6, 7, 8])
+    main([int(a) for a in sys.argv[1:]] or [1, 2, 3, 4, 5, 6, 7, 8])
