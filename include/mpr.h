@@ -92,6 +92,18 @@ mpr_status mpr_transfer_words(int m, uint8_t *words_host, int64_t capacity_words
  * the previous column, p the next), else MPR_INF.  1 <= m <= 11. */
 mpr_status mpr_build_transfer(int m, uint16_t *A, int64_t lda, mpr_stream stream);
 
+/* Border ("loss") matrix of the appendix (proof of Lemma 10) for a strip
+ * of m rows: same states; rows 1..m-1 follow the rule lists above, and the
+ * m-th row need not be dominated (after q_m = d every label allowed after
+ * q_m = c is allowed).  Arc label 10 p(a) + 5 p(b) - 2 nd(q, p), with nd the
+ * newly dominated vertices of Algorithm 3, so a closed walk of n arcs weighs
+ * 5 g - 2 |D(g)| = 2 L_a of the almost Roman dominating function g it
+ * encodes.  Labels can be negative, so every finite entry is written plus
+ * *shift_host = 2 (3m + 1) (host output): traces of the n-th power exceed
+ * 2 L_a(n) by n * shift, and a period (mu, lam, c') found on this matrix has
+ * c = c' - lam * shift.  Device matrix n x n (lda), 1 <= m <= 11. */
+mpr_status mpr_build_border_transfer(int m, uint16_t *A, int64_t lda, int64_t *shift_host, mpr_stream stream);
+
 /* ------------------------------------------------------------------ */
 /* (min,+) products (Section 3).                                       */
 /* ------------------------------------------------------------------ */

@@ -24,6 +24,12 @@ Functions and the passages they follow:
   trace(N, R)                 Corollary 7
   find_period(A, kmax)        Lemma 2 / Proposition 8 / Algorithm 2
   gamma_from_period(...)      the finite-difference solution after Prop. 8
+  border_transfer(m)          the appendix's border matrix: modified last-row
+                              rule, Algorithm 3 (newly dominated vertices),
+                              label 10 p(a) + 5 p(b) - 2 nd(q, p)
+  border_loss_columns(n, m)   the same minimum by a DP over pairs of column
+                              labellings (no word reduction, no Algorithm 3)
+  brute_border_loss(m, n)     Definition 14 + the loss, exhaustively
   brute_gamma(m, n)           definition of a Roman dominating function
   rowdp_gamma(m, n)           exact DP along the path axis (independent)
 """
@@ -81,6 +87,10 @@ def lib():
         L.oracle_minplus_at.argtypes = [i64, i64, p, p, p, p, i64, p]
         L.oracle_transfer_rows.restype = ctypes.c_int
         L.oracle_transfer_rows.argtypes = [ctypes.c_int, p, i64, p]
+        L.oracle_border_transfer.restype = ctypes.c_int
+        L.oracle_border_transfer.argtypes = [ctypes.c_int, p]
+        L.oracle_brute_border_loss.restype = i64
+        L.oracle_brute_border_loss.argtypes = [ctypes.c_int, ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_threads.argtypes = []
         L.oracle_rowdp_gamma.restype = i64
@@ -335,3 +345,59 @@ def rowdp_gamma(m: int, n: int) -> int:
     if v < 0:
         raise ValueError("n out of range for the row DP")
     return int(v)
+
+
+# ---------------------------------------------------------------- border (loss) matrix
+def border_transfer(m: int) -> np.ndarray:
+    """The appendix's border matrix for a strip of m rows (signed int64, INF)."""
+    n = len(words(m))
+    A = np.empty((n, n), dtype=np.int64)
+    if lib().oracle_border_transfer(m, _ptr(A)) != 0:
+        raise RuntimeError("oracle_border_transfer failed")
+    return A
+
+
+def brute_border_loss(m: int, n: int) -> int:
+    """min over almost Roman dominating functions g of 5 g - 2 |D(g)|."""
+    v = lib().oracle_brute_border_loss(m, n)
+    if v == np.iinfo(np.int64).min:
+        raise ValueError("too large for brute force")
+    return int(v)
+
+
+def border_loss_columns(ns, m: int = 4):
+    """min of 5 g - 2 |D(g)| over almost Roman dominating functions of the
+    m-row strip, for each n in ns, by a transfer matrix over PAIRS of
+    consecutive column labellings (3^m each): the arc (a, b) -> (b, c) is
+    allowed when every zero of b outside row m has a 2 next to it (in b, or
+    in a or c on its row) and costs 5 w(b) - 2 (dominated vertices of b +
+    2s in b's row m, which dominate the vertex below the strip).  The trace
+    of its n-th power is the minimum over cyclic sequences of n columns."""
+    L = 3 ** m
+    cols = np.array(list(np.ndindex(*([3] * m))), dtype=np.int64)  # (L, m)
+    two = cols == 2
+    vert2 = np.zeros_like(two)
+    vert2[:, 1:] |= two[:, :-1]
+    vert2[:, :-1] |= two[:, 1:]
+    S = L * L
+    M = np.full((S, S), INF, dtype=np.int64)
+    w = cols.sum(1)
+    for a in range(L):
+        for b in range(L):
+            nb = vert2[b][None, :] | two[a][None, :] | two  # b's rows next to a 2, for every c
+            ok = ~np.any((cols[b][None, :m - 1] == 0) & ~nb[:, :m - 1], axis=1)
+            dom = ((cols[b][None, :] > 0) | nb).sum(1) + int(two[b][m - 1])
+            cost = 5 * w[b] - 2 * dom
+            cs = np.flatnonzero(ok)
+            M[a * L + b, b * L + cs] = cost[cs]
+    out = {}
+    ns = sorted(ns)
+    N, R = normalise(M)
+    k = 1
+    for target in ns:
+        while k < target:
+            N, r = normalise(minplus(N, M))
+            R = add_offsets(R, r)
+            k += 1
+        out[target] = trace(N, R)
+    return out

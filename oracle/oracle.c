@@ -416,3 +416,111 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Border ("loss") matrix of the appendix (proof of Lemma 10).         */
+/* ------------------------------------------------------------------ */
+
+/* Last-row rule of the border version: the m-th row need not be
+ * dominated, so after q_m = d every label the other cases allow is
+ * allowed.  (The printed q_m = b case says "p_3 = d"; read p_m = d, as in
+ * the main text.) */
+static int last_row_rule_border(int qm, int pm, int nb_a)
+{
+    if (qm == LD) return pm == LA || pm == LB || (pm == LC && nb_a) || pm == LD;
+    return row_rule(qm, pm, nb_a);
+}
+
+int oracle_follows_border(const uint8_t *q, const uint8_t *p, int m)
+{
+    for (int i = 0; i < m; i++) {
+        int nb_a = 0;
+        if (i > 0 && p[i - 1] == LA) nb_a = 1;
+        if (i + 1 < m && p[i + 1] == LA) nb_a = 1;
+        int ok = (i == m - 1) ? last_row_rule_border(q[i], p[i], nb_a) : row_rule(q[i], p[i], nb_a);
+        if (!ok) return 0;
+    }
+    return 1;
+}
+
+/* Algorithm 3: newly dominated vertices nd(q, p), rows 1..m, then one more
+ * when p_m = a (the vertex below the border, outside it, is dominated). */
+int64_t oracle_newly_dominated(const uint8_t *q, const uint8_t *p, int m)
+{
+    int64_t nd = 0;
+    for (int i = 0; i < m; i++) {
+        int qi = q[i], pi = p[i];
+        if (qi == LA && pi == LA) nd += 1;
+        else if (qi == LB && pi == LC) nd += 1;
+        else if (qi == LC && pi == LA) nd += 2;
+        else if ((qi == LC || qi == LD) && (pi == LB || pi == LC)) nd += 1;
+        else if (qi == LD && pi == LA) nd += 3;
+    }
+    if (p[m - 1] == LA) nd += 1;
+    return nd;
+}
+
+/* Border matrix: label 10 p(a) + 5 p(b) - 2 nd(q, p) on arcs, else
+ * infinite.  Entries may be negative. */
+int oracle_border_transfer(int m, int64_t *A)
+{
+    int64_t n = oracle_words(m, NULL);
+    if (n < 0) return -1;
+    uint8_t *w = (uint8_t *)malloc((size_t)(n * m));
+    if (!w) return -2;
+    oracle_words(m, w);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t qi = 0; qi < n; qi++)
+        for (int64_t pi = 0; pi < n; pi++) {
+            const uint8_t *q = w + qi * m, *p = w + pi * m;
+            int64_t v = ORACLE_INF;
+            if (oracle_follows_border(q, p, m)) {
+                int64_t na = 0, nb = 0;
+                for (int i = 0; i < m; i++) { na += p[i] == LA; nb += p[i] == LB; }
+                v = 10 * na + 5 * nb - 2 * oracle_newly_dominated(q, p, m);
+            }
+            A[qi * n + pi] = v;
+        }
+    free(w);
+    return 0;
+}
+
+/*
+ * Exhaustive minimum of 5 g(P_m x C_n) - 2 |D(g)| over almost Roman
+ * dominating functions g of the border strip (Definition 14): every zero
+ * outside the m-th row has a neighbour with 2; D(g) = R1 u N[R2] taken in
+ * the larger cylinder, so a 2 in the m-th row also dominates the vertex
+ * below the strip.  Feasible for m*n <= 20.
+ */
+int64_t oracle_brute_border_loss(int m, int n)
+{
+    int V = m * n;
+    if (m < 1 || n < 3 || V > 20) return INT64_MIN;
+    int64_t total = 1;
+    for (int v = 0; v < V; v++) total *= 3;
+    int64_t best = ORACLE_INF;
+#pragma omp parallel for schedule(static) reduction(min : best)
+    for (int64_t code = 0; code < total; code++) {
+        uint8_t f[32];
+        int64_t c = code, g = 0;
+        for (int v = 0; v < V; v++) { f[v] = (uint8_t)(c % 3); c /= 3; g += f[v]; }
+        int ok = 1;
+        int64_t D = 0;
+        for (int i = 0; i < m; i++)
+            for (int j = 0; j < n; j++) {
+                int nb2 = 0;
+                if (f[i * n + (j + 1) % n] == 2) nb2 = 1;
+                if (f[i * n + (j + n - 1) % n] == 2) nb2 = 1;
+                if (i > 0 && f[(i - 1) * n + j] == 2) nb2 = 1;
+                if (i + 1 < m && f[(i + 1) * n + j] == 2) nb2 = 1;
+                int v = f[i * n + j];
+                if (v == 0 && !nb2 && i < m - 1) ok = 0;
+                if (v > 0 || nb2) D++;
+                if (i == m - 1 && v == 2) D++; /* the vertex below the strip */
+            }
+        if (!ok) continue;
+        int64_t loss = 5 * g - 2 * D;
+        if (loss < best) best = loss;
+    }
+    return best;
+}

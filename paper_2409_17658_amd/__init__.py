@@ -75,6 +75,7 @@ _SIGS = {
     "mpr_transfer_size": (_I, [_I, _P]),
     "mpr_transfer_words": (_I, [_I, _P, _I64]),
     "mpr_build_transfer": (_I, [_I, _P, _I64, _P]),
+    "mpr_build_border_transfer": (_I, [_I, _P, _I64, _P, _P]),
     "mpr_minplus_gemm": (_I, [_I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
     "mpr_minplus_gemm_cfg": (_I, [_I, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
     "mpr_normalise": (_I, [_I64, _I64, _P, _I64, _P, _P, _P, _P]),
@@ -228,6 +229,17 @@ def build_transfer(m: int, out=None, stream=None):
     A = alloc_matrix(n, n) if out is None else out
     _ok(lib().mpr_build_transfer(m, _ptr(A), _ld(A), _stream(stream)), "mpr_build_transfer")
     return A
+
+
+def build_border_transfer(m: int, out=None, stream=None):
+    """(A', shift): the appendix's border matrix with every finite entry
+    raised by shift (labels can be negative)."""
+    n = transfer_size(m)
+    A = alloc_matrix(n, n) if out is None else out
+    sh = ctypes.c_int64()
+    _ok(lib().mpr_build_border_transfer(m, _ptr(A), _ld(A), ctypes.byref(sh), _stream(stream)),
+        "mpr_build_border_transfer")
+    return A, sh.value
 
 
 def minplus_gemm(A, B, C=None, check=True, cfg=-1, stream=None, d_status=None):

@@ -14,6 +14,8 @@
 namespace mpr {
 
 mpr_status transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s);
+mpr_status border_transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s);
+int border_shift(int m);
 int64_t transfer_size(int m);
 void transfer_words(int m, uint8_t *out, int64_t count);
 
@@ -268,6 +270,17 @@ extern "C" mpr_status mpr_build_transfer(int m, uint16_t *A, int64_t lda, mpr_st
     if (e != MPR_OK) return e;
     if (lda < transfer_size(m)) return MPR_EINVAL;
     return transfer_launch(m, A, lda, as_stream(stream));
+}
+
+extern "C" mpr_status mpr_build_border_transfer(int m, uint16_t *A, int64_t lda, int64_t *shift_host,
+                                                mpr_stream stream)
+{
+    if (m < 1 || m > 11 || !A || !shift_host) return MPR_EINVAL;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    if (lda < transfer_size(m)) return MPR_EINVAL;
+    *shift_host = border_shift(m);
+    return border_transfer_launch(m, A, lda, as_stream(stream));
 }
 
 static mpr_status gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B, int64_t ldb,

@@ -37,27 +37,51 @@ struct BatchItem {
 using BCfg0 = TileCfg<64, 128, 32, 4, 8>;   // 256 threads, 64-row panels
 using BCfg1 = TileCfg<32, 128, 32, 4, 8>;   // 128 threads, 32-row panels
 using BCfg2 = TileCfg<128, 128, 32, 8, 8>;  // 256 threads, 128-row panels
+using BCfg3 = TileCfg<64, 128, 32, 8, 8>;   // 128 threads, 64-row panels, 8x8 per lane
+using BCfg4 = TileCfg<64, 256, 32, 8, 16>;  // 128 threads, 64-row panels, 8x16 per lane
 
 __device__ __forceinline__ void agent_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void agent_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Rewrites rows [r0, r0+rows) of src (raw values) into dst, subtracting the
 // row minima in rmin[] (infinity stays) and adding them to R (or setting R
-// when first).  Flags normalised values above MPR_FMAX.
+// when first).  Flags normalised values above MPR_FMAX.  Rows are walked in
+// 8-element chunks (16-byte accesses when `vec`).
+__device__ __forceinline__ uint32_t sub_keep_inf(uint32_t v, uint32_t r)
+{
+    return (r == 0xFFFFu || v == 0xFFFFu) ? v : v - r;
+}
+
 template <int NT>
 __device__ void panel_normalise(const u16 *src, int64_t lds_, u16 *dst, int64_t ldd, int64_t r0, int rows, int64_t n,
-                                const uint32_t *rmin, int64_t *R, bool first, int32_t *st)
+                                const uint32_t *rmin, int64_t *R, bool first, bool vec, int32_t *st)
 {
     bool over = false;
-    const int64_t total = (int64_t)rows * n;
+    const int64_t cpr = (n + 7) / 8;  // chunks per row
+    const int64_t total = (int64_t)rows * cpr;
     for (int64_t t = threadIdx.x; t < total; t += NT) {
-        const int rr = (int)(t / n);
-        const int64_t j = t % n;
+        const int rr = (int)(t / cpr);
+        const int64_t j0 = (t % cpr) * 8;
         const uint32_t r = rmin[rr];
-        uint32_t v = src[(r0 + rr) * lds_ + j];
-        if (r != 0xFFFFu && v != 0xFFFFu) v -= r;
-        over |= v != 0xFFFFu && v > FMAX16;
-        dst[(r0 + rr) * ldd + j] = (u16)v;
+        const u16 *sp = src + (r0 + rr) * lds_ + j0;
+        u16 *dp = dst + (r0 + rr) * ldd + j0;
+        if (vec && j0 + 8 <= n) {
+            const uint4 v = *(const uint4 *)sp;
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t lo = sub_keep_inf(w[q] & 0xFFFFu, r), hi = sub_keep_inf(w[q] >> 16, r);
+                over |= (lo != 0xFFFFu && lo > FMAX16) || (hi != 0xFFFFu && hi > FMAX16);
+                w[q] = lo | (hi << 16);
+            }
+            *(uint4 *)dp = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+            for (int64_t j = j0; j < j0 + 8 && j < n; j++) {
+                const uint32_t x = sub_keep_inf(sp[j - j0], r);
+                over |= x != 0xFFFFu && x > FMAX16;
+                dp[j - j0] = (u16)x;
+            }
+        }
     }
     for (int rr = threadIdx.x; rr < rows; rr += NT) {
         const uint32_t r = rmin[rr];
@@ -68,6 +92,29 @@ __device__ void panel_normalise(const u16 *src, int64_t lds_, u16 *dst, int64_t 
             Rv = (r == 0xFFFFu || Rv == ROW_NONE) ? ROW_NONE : Rv + (int64_t)r;
     }
     if (over) set_status(st, MPR_EOVERFLOW);
+}
+
+// Row minima of rows [r0, r0+rows) of A into rmin[] (already 0xFFFF).
+template <int NT>
+__device__ void panel_rowmin(const u16 *A, int64_t lda, int64_t r0, int rows, int64_t n, uint32_t *rmin, bool vec)
+{
+    const int64_t cpr = (n + 7) / 8;
+    const int64_t total = (int64_t)rows * cpr;
+    for (int64_t t = threadIdx.x; t < total; t += NT) {
+        const int rr = (int)(t / cpr);
+        const int64_t j0 = (t % cpr) * 8;
+        const u16 *sp = A + (r0 + rr) * lda + j0;
+        uint32_t m = 0xFFFFu;
+        if (vec && j0 + 8 <= n) {
+            const uint4 v = *(const uint4 *)sp;
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) m = min(m, min(w[q] & 0xFFFFu, w[q] >> 16));
+        } else {
+            for (int64_t j = j0; j < j0 + 8 && j < n; j++) m = min(m, (uint32_t)sp[j - j0]);
+        }
+        atomicMin(&rmin[rr], m);
+    }
 }
 
 template <class T>
@@ -93,18 +140,15 @@ __global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict
         const int64_t ld[2] = {c.ldo, c.ldp};
         int b = (int)((c.e - 1) & 1);
 
+        const bool vec = ((uintptr_t)c.A % 16 == 0) && c.lda % 8 == 0 && ((uintptr_t)c.N_out % 16 == 0) &&
+                         c.ldo % 8 == 0 && ((uintptr_t)c.P % 16 == 0) && c.ldp % 8 == 0;
         // Step 1: the panel of A itself, normalised.
         for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
         __syncthreads();
-        for (int64_t t = threadIdx.x; t < (int64_t)rows * n; t += T::NT) {
-            const int rr = (int)(t / n);
-            atomicMin(&rmin[rr], (uint32_t)c.A[(r0 + rr) * c.lda + t % n]);
-        }
+        panel_rowmin<T::NT>(c.A, c.lda, r0, rows, n, rmin, vec);
         __syncthreads();
-        panel_normalise<T::NT>(c.A, c.lda, buf[b], ld[b], r0, rows, n, rmin, c.R_out, true, st);
+        panel_normalise<T::NT>(c.A, c.lda, buf[b], ld[b], r0, rows, n, rmin, c.R_out, true, vec, st);
 
-        const bool vec = ((uintptr_t)c.A % 16 == 0) && c.lda % 8 == 0 && ((uintptr_t)c.N_out % 16 == 0) &&
-                         c.ldo % 8 == 0 && ((uintptr_t)c.P % 16 == 0) && c.ldp % 8 == 0;
         for (int64_t k = 2; k <= c.e; k++) {
             agent_release();
             __syncthreads();
@@ -137,7 +181,7 @@ __global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict
             agent_release();
             __syncthreads();
             agent_acquire();
-            panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, st);
+            panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, vec, st);
             b = nb;
         }
         agent_release();
@@ -156,6 +200,8 @@ static const BatchCfgInfo kBatchCfgs[] = {
     {BCfg0::BM, BCfg0::NT, (const void *)batch_kernel<BCfg0>},
     {BCfg1::BM, BCfg1::NT, (const void *)batch_kernel<BCfg1>},
     {BCfg2::BM, BCfg2::NT, (const void *)batch_kernel<BCfg2>},
+    {BCfg3::BM, BCfg3::NT, (const void *)batch_kernel<BCfg3>},
+    {BCfg4::BM, BCfg4::NT, (const void *)batch_kernel<BCfg4>},
 };
 static constexpr int kNumBatchCfgs = (int)(sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]));
 

@@ -52,7 +52,24 @@ __device__ __forceinline__ uint64_t entry_hash(int64_t i, int64_t j, uint32_t v)
     return mix64(((uint64_t)i << 40) ^ ((uint64_t)j << 16) ^ (uint64_t)v ^ 0x6A09E667F3BCC909ull);
 }
 
+// Subtract r from a packed pair, keeping infinity; flags results > FMAX.
+__device__ __forceinline__ uint32_t sub_pair(uint32_t w, uint32_t r, bool &over)
+{
+    uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+    lo = lo == 0xFFFFu ? lo : lo - r;
+    hi = hi == 0xFFFFu ? hi : hi - r;
+    over |= (lo != 0xFFFFu && lo > FMAX16) || (hi != 0xFFFFu && hi > FMAX16);
+    return lo | (hi << 16);
+}
+
+__device__ __forceinline__ uint32_t min_pair(uint32_t m, uint32_t w) { return min(m, min(w & 0xFFFFu, w >> 16)); }
+
+constexpr int NCH = 12;  // 16-byte chunks a thread keeps in registers
+
 // One block per row: r = least finite entry, row -= r, R_out = R_in + r (+ add).
+// Rows of up to RB * 8 * NCH entries (24576) are read from HBM once and kept
+// in registers between the minimum and the subtraction; longer rows are read
+// twice.
 __global__ __launch_bounds__(RB) void normalise_kernel(u16 *C, int64_t ldc, int64_t N, const int64_t *R_in,
                                                        const int64_t *add_scalar, int64_t *R_out, int32_t *st,
                                                        uint64_t *row_hash, int vec)
@@ -61,16 +78,33 @@ __global__ __launch_bounds__(RB) void normalise_kernel(u16 *C, int64_t ldc, int6
     const int64_t i = blockIdx.x;
     u16 *row = C + i * ldc;
     uint32_t mn = 0xFFFFu;
-    if (vec) {
+    const bool resident = vec && N <= (int64_t)RB * 8 * NCH;
+    uint4 keep[NCH];
+    if (resident) {
+#pragma unroll
+        for (int q = 0; q < NCH; q++) {
+            const int64_t c = ((int64_t)threadIdx.x + (int64_t)q * RB) * 8;
+            keep[q] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+            if (c + 8 <= N) {
+                keep[q] = *(const uint4 *)(row + c);
+            } else if (c < N) {
+                uint32_t w[4];
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t lo = c + 2 * e < N ? row[c + 2 * e] : 0xFFFFu;
+                    const uint32_t hi = c + 2 * e + 1 < N ? row[c + 2 * e + 1] : 0xFFFFu;
+                    w[e] = lo | (hi << 16);
+                }
+                keep[q] = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+            mn = min_pair(min_pair(mn, keep[q].x), keep[q].y);
+            mn = min_pair(min_pair(mn, keep[q].z), keep[q].w);
+        }
+    } else if (vec) {
         for (int64_t c = (int64_t)threadIdx.x * 8; c < N; c += RB * 8) {
             if (c + 8 <= N) {
                 const uint4 v = *(const uint4 *)(row + c);
-                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    mn = min(mn, w[q] & 0xFFFFu);
-                    mn = min(mn, w[q] >> 16);
-                }
+                mn = min_pair(min_pair(mn, v.x), v.y);
+                mn = min_pair(min_pair(mn, v.z), v.w);
             } else {
                 for (int64_t j = c; j < N; j++) mn = min(mn, (uint32_t)row[j]);
             }
@@ -88,19 +122,36 @@ __global__ __launch_bounds__(RB) void normalise_kernel(u16 *C, int64_t ldc, int6
     uint64_t h = 0;
     bool over = false;
     if (r != 0xFFFFu) {
-        if (vec) {
+        if (resident) {
+#pragma unroll
+            for (int q = 0; q < NCH; q++) {
+                const int64_t c = ((int64_t)threadIdx.x + (int64_t)q * RB) * 8;
+                if (c >= N) continue;
+                uint32_t w[4] = {keep[q].x, keep[q].y, keep[q].z, keep[q].w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    w[e] = sub_pair(w[e], r, over);
+                    if (row_hash) {
+                        if (c + 2 * e < N) h += entry_hash(i, c + 2 * e, w[e] & 0xFFFFu);
+                        if (c + 2 * e + 1 < N) h += entry_hash(i, c + 2 * e + 1, w[e] >> 16);
+                    }
+                }
+                if (c + 8 <= N) {
+                    *(uint4 *)(row + c) = make_uint4(w[0], w[1], w[2], w[3]);
+                } else {
+                    for (int e = 0; e < 8 && c + e < N; e++) row[c + e] = (u16)(w[e >> 1] >> ((e & 1) * 16));
+                }
+            }
+        } else if (vec) {
             for (int64_t c = (int64_t)threadIdx.x * 8; c < N; c += RB * 8) {
                 if (c + 8 <= N) {
                     uint4 v = *(const uint4 *)(row + c);
                     uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                     for (int q = 0; q < 4; q++) {
-                        uint32_t lo = w[q] & 0xFFFFu, hi = w[q] >> 16;
-                        lo = lo == 0xFFFFu ? lo : lo - r;
-                        hi = hi == 0xFFFFu ? hi : hi - r;
-                        over |= (lo != 0xFFFFu && lo > FMAX16) || (hi != 0xFFFFu && hi > FMAX16);
-                        if (row_hash) h += entry_hash(i, c + 2 * q, lo) + entry_hash(i, c + 2 * q + 1, hi);
-                        w[q] = lo | (hi << 16);
+                        w[q] = sub_pair(w[q], r, over);
+                        if (row_hash)
+                            h += entry_hash(i, c + 2 * q, w[q] & 0xFFFFu) + entry_hash(i, c + 2 * q + 1, w[q] >> 16);
                     }
                     *(uint4 *)(row + c) = make_uint4(w[0], w[1], w[2], w[3]);
                 } else {

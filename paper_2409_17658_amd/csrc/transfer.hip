@@ -98,6 +98,55 @@ __global__ __launch_bounds__(256) void transfer_kernel(WordTable t, int64_t n, u
     }
 }
 
+// Border ("loss") matrix of the appendix for a strip of m rows.  Rows
+// 1..m-1 follow the rule lists above; the m-th row need not be dominated,
+// so after q_m = d everything allowed after q_m = c is allowed.  The arc
+// label is 10 p(a) + 5 p(b) - 2 nd(q, p), nd(q, p) = newly dominated
+// vertices by Algorithm 3 (per row: (a,a) 1, (b,c) 1, (c,a) 2, (c|d, b|c) 1,
+// (d,a) 3; plus 1 when p_m = a, for the vertex below the strip).  Labels
+// can be negative down to -2 (3m + 1); entries are stored shifted by
+// shift = 2 (3m + 1) so that they fit uint16, and every closed walk of n
+// arcs then weighs n * shift more.
+__global__ __launch_bounds__(256) void border_transfer_kernel(WordTable t, int64_t n, u16 *A, int64_t lda, int shift)
+{
+    const int64_t q = blockIdx.x;
+    const uint32_t wq = unrank(t, q);
+    const int m = t.m;
+    for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
+        const uint32_t wp = unrank(t, p);
+        bool ok = true;
+        int label = 0, nd = 0;
+        for (int i = 0; i < m; i++) {
+            const int qi = (wq >> (2 * i)) & 3, pi = (wp >> (2 * i)) & 3;
+            const bool a_up = i > 0 && ((wp >> (2 * (i - 1))) & 3) == 0;
+            const bool a_down = i + 1 < m && ((wp >> (2 * (i + 1))) & 3) == 0;
+            const int qr = (i == m - 1 && qi == 3) ? 2 : qi;  // last row: d behaves like c
+            const uint32_t allowed = kAlways[qr] | ((a_up || a_down) ? kWithA[qr] : 0);
+            ok = ok && ((allowed >> pi) & 1u);
+            label += pi == 0 ? 10 : (pi == 1 ? 5 : 0);
+            if (qi == 0 && pi == 0) nd += 1;
+            else if (qi == 1 && pi == 2) nd += 1;
+            else if (qi == 2 && pi == 0) nd += 2;
+            else if (qi >= 2 && (pi == 1 || pi == 2)) nd += 1;
+            else if (qi == 3 && pi == 0) nd += 3;
+        }
+        if (((wp >> (2 * (m - 1))) & 3) == 0) nd += 1;
+        A[q * lda + p] = ok ? (u16)(label - 2 * nd + shift) : (u16)0xFFFF;
+    }
+}
+
+int border_shift(int m) { return 2 * (3 * m + 1); }
+
+mpr_status border_transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s)
+{
+    WordTable t;
+    make_table(m, t);
+    const int64_t n = word_count(t);
+    if (lda < n) return MPR_EINVAL;
+    hipLaunchKernelGGL(border_transfer_kernel, dim3((unsigned)n), dim3(256), 0, s, t, n, A, lda, border_shift(m));
+    return check_launch();
+}
+
 mpr_status transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s)
 {
     WordTable t;

@@ -129,6 +129,19 @@ def test_normalise_matches_oracle(mpr):
     assert np.array_equal(Rout.cpu().numpy(), R)
 
 
+@pytest.mark.parametrize("rows,cols,pad", [(5, 16384, 0), (3, 24583, 0), (2, 30001, 7), (4, 1000, 1), (3, 7, 0)])
+def test_normalise_row_lengths(mpr, rows, cols, pad):
+    """Register-resident rows (<= 24576 entries), two-pass rows, odd strides."""
+    X = synth.random_matrix(rows, cols, 31 + cols, 2, 700, 0.3)
+    X[0, :] = 0xFFFF
+    buf = np.full((rows, cols + pad), 0xFFFF, dtype=np.uint16)
+    buf[:, :cols] = X
+    C = torch.from_numpy(buf).cuda()[:, :cols] if pad else _dev(mpr, X)
+    Rout = mpr.normalise(C)
+    N, r = O.normalise(O.from_u16(X))
+    assert np.array_equal(_host(C), _u16(N)) and np.array_equal(Rout.cpu().numpy(), r)
+
+
 def test_gemm_norm_product_of_powers(mpr):
     A = O.transfer(4)
     Pa = O.power_chain(A, 5)

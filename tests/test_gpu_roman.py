@@ -55,3 +55,26 @@ def test_chain_and_squaring_digests(mpr, m):
                 continue
             N, R = mpr.minplus_power(A, k, sched)
             assert digest(N, R) == g["digest_sha256"][str(k)], (k, sched)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7])
+def test_border_transfer_bit_exact(mpr, m):
+    import oracle as O
+
+    A, shift = mpr.build_border_transfer(m)
+    ref = O.border_transfer(m)
+    got = A.cpu().numpy().astype(np.int64)
+    fin = ref != O.INF
+    assert np.array_equal(got == 0xFFFF, ~fin)
+    assert np.array_equal(got[fin] - shift, ref[fin])
+
+
+def test_border_m4_period_and_loss(mpr, paper_values):
+    """Appendix: Algorithm 2 on the border matrix, m = 4: (30, 1, 1); the
+    traces minus n * shift are 2 L_a(n) = n for 10 <= n <= 300 except
+    2 L_a(11) = 12 (as the oracle and its column DP give)."""
+    A, shift = mpr.build_border_transfer(4)
+    mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=40)
+    assert (mu, lam, c - lam * shift) == tuple(paper_values["loss_border_m4"]["period"])
+    for n in range(10, 301):
+        assert tr[n] - n * shift == (12 if n == 11 else n), n

@@ -30,7 +30,7 @@ def _small_batch(mpr):
     return chains, mats
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 def test_batch_matches_oracle_and_solo(mpr, cfg):
     print("batch cfg", cfg, flush=True)
     mpr.set_batch_config(cfg)
@@ -90,3 +90,34 @@ def test_batch_graph_replays(mpr):
         del x
     finally:
         mpr.graph_destroy(g)
+
+
+def test_batch_full_config4_sampled_rows(mpr):
+    """The full batched workload (256 chains, N log-uniform in [256, 4096],
+    e in [8, 128], entries U[0,31] with 25% infinity) in the benchmark's
+    launch; rows of three chains checked against the oracle's
+    row-restricted chain, every chain against its solo GPU run."""
+    inst = synth.batch_instances(256, seed=4)
+    chains, mats = [], []
+    for d in inst:
+        X = synth.random_matrix(d["n"], d["n"], d["seed"], 0, 31, 0.25)
+        mats.append(X)
+        chains.append((mpr.to_device(X), d["e"], mpr.alloc_matrix(d["n"], d["n"]),
+                       torch.empty(d["n"], dtype=torch.int64, device="cuda")))
+    print("batch generated", flush=True)
+    mpr.batch_power(chains)
+    torch.cuda.synchronize()
+    print("batch done", flush=True)
+    order = sorted(range(256), key=lambda i: -inst[i]["n"])
+    picks = [order[0], order[128], order[-1]]
+    for i in picks:
+        A, e, N, R = chains[i]
+        n = A.shape[0]
+        rows = [0, n // 2, n - 1]
+        Nr, Rr = O.chain_rows(O.from_u16(mats[i]), rows, e)
+        assert np.array_equal(N.cpu().numpy()[rows], O.to_u16(Nr)), (n, e)
+        assert np.array_equal(R.cpu().numpy()[rows], Rr)
+    ws = mpr.workspace(max(mpr.power_workspace_size(d["n"], d["e"]) for d in inst))
+    for (A, e, N, R) in chains[::8]:
+        Ns, Rs = mpr.minplus_power(A, e, mpr.CHAIN, ws=ws)
+        assert torch.equal(Ns.view(torch.int16), N.view(torch.int16)) and torch.equal(Rs, R)
