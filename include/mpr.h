@@ -208,6 +208,20 @@ mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t km
                            int64_t *mu_host, int64_t *lam_host, int64_t *c_host,
                            int64_t *traces_host, void *ws, size_t ws_bytes, mpr_stream stream);
 
+/* Proposition 8 and the finite-difference solution that follows it: with
+ * A^(mu+lam) = c (x) A^mu, gamma(n + lam) = gamma(n) + c for n >= mu, so
+ *   gamma(n) = traces[mu + (n - mu) mod lam] + c * floor((n - mu) / lam)
+ * for n >= mu, and traces[n] below mu.  traces_host[k] (k <= kmax) are the
+ * traces of A^k as mpr_find_period returns them; needs mu + lam - 1 <= kmax
+ * (and n <= kmax when n < mu).  Host only. */
+mpr_status mpr_gamma_from_period(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
+                                 int64_t kmax, int64_t n, int64_t *gamma_host);
+/* The same solution as a closed form: for n >= mu,
+ *   gamma(n) = (c * n + numer_host[n mod lam]) / lam   (an exact division),
+ * numer_host receiving lam int64 values.  Host only. */
+mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
+                              int64_t kmax, int64_t *numer_host);
+
 /* ------------------------------------------------------------------ */
 /* Batched power chains: one persistent launch.                        */
 /* ------------------------------------------------------------------ */

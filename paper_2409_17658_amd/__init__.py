@@ -88,6 +88,8 @@ _SIGS = {
     "mpr_trace_of_product": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
     "mpr_period_workspace_size": (_I, [_I64, _I64, _P]),
     "mpr_find_period": (_I, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mpr_gamma_from_period": (_I, [_I64, _I64, _I64, _P, _I64, _I64, _P]),
+    "mpr_period_formula": (_I, [_I64, _I64, _I64, _P, _I64, _P]),
     "mpr_batch_workspace_size": (_I, [_P, _I, _P]),
     "mpr_batch_plan": (_I, [_P, _I, _P, _SZ, _P]),
     "mpr_batch_launch": (_I, [_P, _P, _P]),
@@ -349,6 +351,24 @@ def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, str
         return None, None, None, tr
     _ok(st, "mpr_find_period")
     return mu.value, lam.value, c.value, tr
+
+
+def gamma_from_period(mu: int, lam: int, c: int, traces, n: int) -> int:
+    """gamma(n) from a period and the traces (Proposition 8)."""
+    tr = np.ascontiguousarray(traces, dtype=np.int64)
+    g = ctypes.c_int64()
+    _ok(lib().mpr_gamma_from_period(mu, lam, c, tr.ctypes.data_as(_P), len(tr) - 1, n, ctypes.byref(g)),
+        "mpr_gamma_from_period")
+    return g.value
+
+
+def period_formula(mu: int, lam: int, c: int, traces):
+    """numer[r] with gamma(n) = (c n + numer[n mod lam]) / lam for n >= mu."""
+    tr = np.ascontiguousarray(traces, dtype=np.int64)
+    out = np.zeros(lam, dtype=np.int64)
+    _ok(lib().mpr_period_formula(mu, lam, c, tr.ctypes.data_as(_P), len(tr) - 1, out.ctypes.data_as(_P)),
+        "mpr_period_formula")
+    return out
 
 
 # ---------------------------------------------------------------- batched chains

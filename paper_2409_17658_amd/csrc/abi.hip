@@ -487,3 +487,29 @@ extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda,
     *c_host = cval;
     return MPR_OK;
 }
+
+// ------------------------------------------------------------ Proposition 8
+extern "C" mpr_status mpr_gamma_from_period(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
+                                            int64_t kmax, int64_t n, int64_t *gamma_host)
+{
+    if (mu < 1 || lam < 1 || !traces_host || !gamma_host || n < 1 || mu + lam - 1 > kmax) return MPR_EINVAL;
+    if (n < mu) {
+        if (n > kmax) return MPR_EINVAL;
+        *gamma_host = traces_host[n];
+        return MPR_OK;
+    }
+    const int64_t q = (n - mu) / lam, r = (n - mu) % lam;
+    *gamma_host = traces_host[mu + r] + c * q;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
+                                         int64_t kmax, int64_t *numer_host)
+{
+    if (mu < 1 || lam < 1 || !traces_host || !numer_host || mu + lam - 1 > kmax) return MPR_EINVAL;
+    for (int64_t r = 0; r < lam; r++) {
+        const int64_t k = mu + r;  // residue class of k modulo lam
+        numer_host[k % lam] = lam * traces_host[k] - c * k;
+    }
+    return MPR_OK;
+}
