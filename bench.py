@@ -285,6 +285,41 @@ def bench_config3(args, mpr, torch):
             "per_m": per_m}
 
 
+# ---------------------------------------------------------------- m = 10
+def bench_m10(args, mpr, torch):
+    """gamma_R(P_10 x C_n) for every n: the m = 10 transfer matrix (64769
+    states, 8.4 GB per power) by the chain with a ring of 8 resident powers,
+    its least period, and the checks the paper and the oracle provide:
+    Remark 13 (2(m+1)n/5 for 5 | n), Theorem 11 (ceil(2(m+1)n/5) <= gamma for
+    n >= 10) and the oracle's row DP for n <= 9 (stored golden)."""
+    m, kmax = 10, args.m10_kmax
+    A = mpr.build_transfer(m)
+    n = A.shape[0]
+    ws = mpr.workspace(mpr.period_workspace_size(n, 8))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu, lam, c, tr = mpr.find_period(A, kmax, traces=True, ws=ws)
+    t = time.perf_counter() - t0
+    gam = {k: int(tr[k]) for k in range(3, kmax + 1)}
+    out = {"metric": "gamma_R(P_10 x C_n): transfer powers at N=64769", "value": round((kmax - 1) * float(n) ** 3 / t / 1e9, 1),
+           "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16", "data": "transfer matrix m=10",
+           "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n},
+           "period": [mu, lam, c], "seconds": round(t, 1), "gamma": gam}
+    if mu is not None:
+        numer = mpr.period_formula(mu, lam, c, tr[: mu + lam])
+        out["formula"] = {"valid_from": mu, "gamma(n)": "(%d n + numer[n mod %d]) / %d" % (c, lam, lam),
+                          "numer": numer.tolist()}
+        ext = lambda k: mpr.gamma_from_period(mu, lam, c, tr, k)
+        out["remark13_ok"] = all(ext(k) == 2 * (m + 1) * k // 5 for k in range(5, 2001, 5))
+        out["theorem11_ok"] = all(ext(k) >= -(-2 * (m + 1) * k // 5) for k in range(10, 2001))
+    gd = os.path.join(ROOT, "tests", "golden", "rowdp_m10.json")
+    if os.path.exists(gd):
+        with open(gd) as f:
+            rd = {int(k): v for k, v in json.load(f)["gamma"].items()}
+        out["rowdp_golden_ok"] = all(gam[k] == v for k, v in rd.items() if k in gam)
+    return out
+
+
 # ---------------------------------------------------------------- config 4
 def bench_config4(args, mpr, torch):
     import synth
@@ -402,7 +437,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--cfg", type=int, default=-1, help="tile configuration (-1: tile table)")
-    ap.add_argument("--workload", default="gemm", choices=["gemm", "config2", "config3", "config4", "serve"])
+    ap.add_argument("--workload", default="gemm", choices=["gemm", "config2", "config3", "config4", "serve", "m10"])
+    ap.add_argument("--m10-kmax", type=int, default=35)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -436,6 +472,8 @@ def main():
         out = bench_config3(args, mpr, torch)
     elif args.workload == "config4":
         out = bench_config4(args, mpr, torch)
+    elif args.workload == "m10":
+        out = bench_m10(args, mpr, torch)
     else:
         out = {"metric": "gamma_R query serving, Poisson 200 req/s, m in 3..9, n in 3..1000",
                "unit": "ms", "n_gpus": 1, "higher_is_better": False}

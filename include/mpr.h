@@ -191,15 +191,17 @@ mpr_status mpr_trace_of_product(const uint16_t *X, const int64_t *RX,
 /* ------------------------------------------------------------------ */
 
 /* Workspace bytes to keep `slots` powers of an n x n matrix resident
- * (slots >= 2; the search can confirm a period mu + lam only when
- * mu + lam < slots). */
+ * (slots >= 2).  The period search keeps the last `slots` powers in a ring,
+ * so it can confirm a period lam only when lam < slots; mu is unbounded. */
 mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_host);
 
 /* Least (mu, lam, c) with A^(mu+lam) = c (x) A^mu, searching the chain
  * A^1 .. A^kmax.  The classes of A^k up to a scalar shift form an
  * eventually periodic sequence; the first repeated class (found by a
  * 64-bit class hash, then confirmed by an exact compare of (N, R - R'))
- * gives the least pre-period mu and the least period lam.  When traces_host
+ * gives the least pre-period mu and the least period lam (confirmable when
+ * lam is smaller than the number of power slots the workspace holds; the
+ * class hashes of all earlier powers stay on the host).  When traces_host
  * is not NULL it receives kmax + 1 int64 values, traces_host[k] = trace of
  * A^k for k = 1..kmax (the chain then always runs to kmax), else the search
  * stops at the first confirmed repeat.  SYNCHRONOUS on `stream`.  Returns

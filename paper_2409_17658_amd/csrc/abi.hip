@@ -422,22 +422,14 @@ extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda,
     if ((r = validate_launch(A, n, n, lda, st, s)) != MPR_OK) return r;
     if (traces_host) traces_host[0] = MPR_ROW_NONE;
 
-    std::unordered_multimap<uint64_t, int64_t> seen;  // class hash -> k (slot k-1)
-    bool found = false, storing = true;
+    // Power k lives in slot (k - 1) % slots (a ring), so a repeat of the class
+    // of power j can be confirmed exactly while k - j < slots.
+    std::unordered_multimap<uint64_t, int64_t> seen;  // class hash -> k
+    bool found = false;
     int64_t mu = 0, lam = 0, cval = 0;
     int64_t prev_slot = -1;
-    int64_t pp = 0;  // ping-pong selector once slots stop holding every power
     for (int64_t k = 1; k <= kmax; k++) {
-        if (storing && k > w.slots) storing = false;
-        int64_t slot;
-        if (storing) {
-            slot = k - 1;
-        } else {
-            // alternate between the last two slots, never overwriting the input
-            const int64_t a = w.slots - 1, b = w.slots - 2;
-            slot = (prev_slot == a) ? b : a;
-            (void)pp;
-        }
+        const int64_t slot = (k - 1) % w.slots;
         u16 *Nk = slot_N(w, slot);
         int64_t *Rk = slot_R(w, slot);
         if (k == 1) {
@@ -458,14 +450,15 @@ extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda,
         if ((int32_t)(host[2] & 0xFFFFFFFF) != 0) return MPR_EOVERFLOW;
         if (traces_host) traces_host[k] = host[1];
         prev_slot = slot;
-        if (!found && storing) {
+        if (!found) {
             const uint64_t h = (uint64_t)host[0];
             auto range = seen.equal_range(h);
             for (auto it = range.first; it != range.second && !found; ++it) {
                 const int64_t j = it->second;
+                if (k - j >= w.slots) continue;  // power j is no longer resident
                 int64_t *out3 = &w.scal[3];
-                if ((r = compare_launch(slot_N(w, j - 1), slot_R(w, j - 1), Nk, Rk, n, w.ld, out3, s)) != MPR_OK)
-                    return r;
+                const int64_t sj = (j - 1) % w.slots;
+                if ((r = compare_launch(slot_N(w, sj), slot_R(w, sj), Nk, Rk, n, w.ld, out3, s)) != MPR_OK) return r;
                 int64_t cmp[3];
                 if (hipMemcpyAsync(cmp, out3, sizeof(cmp), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
