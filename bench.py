@@ -266,9 +266,23 @@ def bench_config3(args, mpr, torch):
         t_sq = time.perf_counter() - t0
         same = bool(torch.equal(Nc.view(torch.int16), N.view(torch.int16)) and torch.equal(Rc, R))
         mpr.check_status(st)
+        wsp = mpr.workspace(mpr.power_workspace_size(n, 300, mpr.CHAIN_SPARSE))
+        Ns = mpr.alloc_matrix(n, n)
+        Rs = torch.empty(n, dtype=torch.int64, device="cuda")
+        mpr.minplus_power(A, 4, mpr.CHAIN_SPARSE, Ns, Rs, wsp, check=False, d_status=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mpr.minplus_power(A, 300, mpr.CHAIN_SPARSE, Ns, Rs, wsp, check=False, d_status=st)
+        torch.cuda.synchronize()
+        t_sp = time.perf_counter() - t0
+        same_sp = bool(torch.equal(Nc.view(torch.int16), Ns.view(torch.int16)) and torch.equal(Rc, Rs))
         t0 = time.perf_counter()
         mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=40)
         t_per = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mus, lams, cs, trs = mpr.find_period(A, 300, traces=True, slots=8, sparse=True)
+        t_per_sp = time.perf_counter() - t0
+        same_per = (mus, lams, cs) == (mu, lam, c) and bool(np.array_equal(trs, tr))
         ok = None
         if m in goldens:
             g, per = goldens[m]
@@ -276,7 +290,10 @@ def bench_config3(args, mpr, torch):
         per_m[m] = {"n_states": n, "period": [mu, lam, c], "chain_300_s": round(t_chain, 3),
                     "chain_gpairs": round(299 * float(n) ** 3 / t_chain / 1e9, 1),
                     "square_300_s": round(t_sq, 4), "chain_equals_square": same,
-                    "find_period_300_s": round(t_per, 3), "gamma_3_300_match_golden": ok}
+                    "sparse_chain_300_s": round(t_sp, 4), "sparse_speedup": round(t_chain / t_sp, 2),
+                    "sparse_equals_dense": same_sp,
+                    "find_period_300_s": round(t_per, 3), "find_period_sparse_300_s": round(t_per_sp, 3),
+                    "sparse_period_same": same_per, "gamma_3_300_match_golden": ok}
     tot = sum(299 * float(v["n_states"]) ** 3 for v in per_m.values())
     tt = sum(v["chain_300_s"] for v in per_m.values())
     return {"metric": "Roman transfer powers to n=300 (m=6,7,8): chain GOPS", "value": round(tot / tt / 1e9, 1),
@@ -295,15 +312,20 @@ def bench_m10(args, mpr, torch):
     m, kmax = 10, args.m10_kmax
     A = mpr.build_transfer(m)
     n = A.shape[0]
-    ws = mpr.workspace(mpr.period_workspace_size(n, 8))
+    torch.cuda.synchronize()
+    print("m10: transfer matrix built, %d states" % n, file=sys.stderr, flush=True)
+    flags = mpr.PERIOD_SPARSE if args.m10_sparse else 0
+    ws = mpr.workspace(mpr.period_workspace_size(n, 8, flags))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mu, lam, c, tr = mpr.find_period(A, kmax, traces=True, ws=ws)
+    mu, lam, c, tr = mpr.find_period(A, kmax, traces=True, ws=ws, sparse=bool(args.m10_sparse))
     t = time.perf_counter() - t0
+    print("m10: %d powers in %.1f s, period %s" % (kmax, t, (mu, lam, c)), file=sys.stderr, flush=True)
     gam = {k: int(tr[k]) for k in range(3, kmax + 1)}
     out = {"metric": "gamma_R(P_10 x C_n): transfer powers at N=64769", "value": round((kmax - 1) * float(n) ** 3 / t / 1e9, 1),
            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16", "data": "transfer matrix m=10",
-           "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n},
+           "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n,
+                      "chain_step": "compressed-K (sparse A)" if args.m10_sparse else "dense"},
            "period": [mu, lam, c], "seconds": round(t, 1), "gamma": gam}
     if mu is not None:
         numer = mpr.period_formula(mu, lam, c, tr[: mu + lam])
@@ -439,6 +461,7 @@ def main():
     ap.add_argument("--cfg", type=int, default=-1, help="tile configuration (-1: tile table)")
     ap.add_argument("--workload", default="gemm", choices=["gemm", "config2", "config3", "config4", "serve", "m10"])
     ap.add_argument("--m10-kmax", type=int, default=35)
+    ap.add_argument("--m10-sparse", type=int, default=1)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0,

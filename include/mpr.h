@@ -61,6 +61,9 @@ typedef enum {
 #define MPR_ROW_NONE INT64_MAX
 #define MPR_CHAIN 0  /* A^e = (((A (x) A) (x) A) ...): e-1 products */
 #define MPR_SQUARE 1 /* binary powering: squares A^(2^j) and their products */
+#define MPR_CHAIN_SPARSE 2 /* the chain, each step over only the rows of A that
+                            * reach each block of output columns */
+#define MPR_PERIOD_SPARSE 1 /* mpr_find_period_ex flag: compressed-K chain steps */
 
 typedef void *mpr_stream;
 
@@ -167,7 +170,11 @@ mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *
 /* Canonical form (N_out, R_out) of A^e for the n x n matrix A, e >= 1.
  * schedule = MPR_CHAIN computes A^k = A^(k-1) (x) A with A kept raw and a
  * normalisation after every product (e-1 products); MPR_SQUARE uses binary
- * powering on canonical forms.  Both give identical bits.  N_out is n x n
+ * powering on canonical forms; MPR_CHAIN_SPARSE is the chain with each step
+ * restricted, per block of 64 output columns J, to the rows L_J of A that
+ * have a finite entry in J (C[:, J] = N[:, L_J] (x) A[L_J, J], the same
+ * product; worth it when A is sparse, as transfer matrices are).  All three
+ * give identical bits.  N_out is n x n
  * (ldo), R_out has n entries. */
 mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t lda, int64_t e,
                              int schedule, uint16_t *N_out, int64_t ldo, int64_t *R_out,
@@ -223,6 +230,14 @@ mpr_status mpr_gamma_from_period(int64_t mu, int64_t lam, int64_t c, const int64
  * numer_host receiving lam int64 values.  Host only. */
 mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
                               int64_t kmax, int64_t *numer_host);
+
+/* mpr_find_period with flags: MPR_PERIOD_SPARSE runs the chain steps as
+ * MPR_CHAIN_SPARSE does (identical results).  The workspace must then be
+ * sized by mpr_period_workspace_size_ex with the same flags. */
+mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host);
+mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int flags,
+                              int64_t *mu_host, int64_t *lam_host, int64_t *c_host, int64_t *traces_host,
+                              void *ws, size_t ws_bytes, mpr_stream stream);
 
 /* ------------------------------------------------------------------ */
 /* Batched power chains: one persistent launch.                        */

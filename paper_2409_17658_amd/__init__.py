@@ -29,6 +29,8 @@ FMAX = 0x7FFF
 ROW_NONE = (1 << 63) - 1
 CHAIN = 0
 SQUARE = 1
+CHAIN_SPARSE = 2
+PERIOD_SPARSE = 1
 
 _STATUS = {0: "MPR_OK", 1: "MPR_EINVAL", 2: "MPR_ENOMEM", 3: "MPR_EOVERFLOW",
            4: "MPR_ENOTFOUND", 5: "MPR_EHIP", 6: "MPR_EUNSUPPORTED"}
@@ -88,6 +90,8 @@ _SIGS = {
     "mpr_trace_of_product": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
     "mpr_period_workspace_size": (_I, [_I64, _I64, _P]),
     "mpr_find_period": (_I, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mpr_period_workspace_size_ex": (_I, [_I64, _I64, _I, _P]),
+    "mpr_find_period_ex": (_I, [_P, _I64, _I64, _I64, _I, _P, _P, _P, _P, _P, _SZ, _P]),
     "mpr_gamma_from_period": (_I, [_I64, _I64, _I64, _P, _I64, _I64, _P]),
     "mpr_period_formula": (_I, [_I64, _I64, _I64, _P, _I64, _P]),
     "mpr_batch_workspace_size": (_I, [_P, _I, _P]),
@@ -331,22 +335,25 @@ def trace_of_product(X, RX, Y, RY, out=None, stream=None):
     return out
 
 
-def period_workspace_size(n: int, slots: int) -> int:
+def period_workspace_size(n: int, slots: int, flags: int = 0) -> int:
     nb = ctypes.c_size_t()
-    _ok(lib().mpr_period_workspace_size(n, slots, ctypes.byref(nb)), "mpr_period_workspace_size")
+    _ok(lib().mpr_period_workspace_size_ex(n, slots, flags, ctypes.byref(nb)), "mpr_period_workspace_size_ex")
     return nb.value
 
 
-def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None):
+def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None, sparse: bool = False):
     """(mu, lam, c, traces) with traces[k] = trace of A^k for k = 1..kmax
-    (None when traces=False); mu is None when no period is confirmed."""
+    (None when traces=False); mu is None when no period is confirmed.
+    sparse=True runs the chain steps over the compressed rows of A."""
     n = A.shape[0]
+    flags = PERIOD_SPARSE if sparse else 0
     if ws is None:
-        ws = workspace(period_workspace_size(n, slots), A.device)
+        ws = workspace(period_workspace_size(n, slots, flags), A.device)
     mu, lam, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     tr = np.zeros(kmax + 1, dtype=np.int64) if traces else None
-    st = lib().mpr_find_period(_ptr(A), n, _ld(A), kmax, ctypes.byref(mu), ctypes.byref(lam), ctypes.byref(c),
-                               tr.ctypes.data_as(_P) if traces else None, _ptr(ws), ws.numel(), _stream(stream))
+    st = lib().mpr_find_period_ex(_ptr(A), n, _ld(A), kmax, flags, ctypes.byref(mu), ctypes.byref(lam),
+                                  ctypes.byref(c), tr.ctypes.data_as(_P) if traces else None, _ptr(ws), ws.numel(),
+                                  _stream(stream))
     if st == 4:
         return None, None, None, tr
     _ok(st, "mpr_find_period")

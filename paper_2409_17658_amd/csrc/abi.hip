@@ -108,6 +108,7 @@ static size_t gemm_norm_ws(int64_t K, int64_t N, int64_t *ldp_out)
 struct PowerWs {
     u16 *P, *acc, *Bp, *C;
     int64_t *RP, *Racc, *RC, *s;
+    void *plan;  // compressed-K plan of A (MPR_CHAIN_SPARSE)
     int64_t ld;
     size_t bytes;
 };
@@ -127,12 +128,13 @@ static PowerWs carve_power(void *ws, int64_t n, int schedule)
         w.RC = c.take<int64_t>((size_t)n);
         w.s = c.take<int64_t>(1);
     }
+    if (schedule == MPR_CHAIN_SPARSE) w.plan = c.take<char>(sparse_plan_bytes(n));
     w.bytes = c.used + 256;
     return w;
 }
 
 static mpr_status power_chain(const u16 *A, int64_t n, int64_t lda, int64_t e, u16 *N_out, int64_t ldo,
-                              int64_t *R_out, const PowerWs &w, int32_t *st, hipStream_t s)
+                              int64_t *R_out, const PowerWs &w, int32_t *st, hipStream_t s, bool sparse)
 {
     // Step k writes buffer (e - k) % 2, so step e lands in N_out.
     u16 *buf[2] = {N_out, w.P};
@@ -140,9 +142,11 @@ static mpr_status power_chain(const u16 *A, int64_t n, int64_t lda, int64_t e, u
     int b = (int)((e - 1) & 1);
     mpr_status r = copy_launch(A, lda, buf[b], ld[b], n, n, s);
     if (r == MPR_OK) r = normalise_launch(n, n, buf[b], ld[b], nullptr, nullptr, R_out, st, nullptr, s);
+    if (r == MPR_OK && sparse && e >= 2) r = sparse_plan_launch(A, n, lda, w.plan, s);
     for (int64_t k = 2; k <= e && r == MPR_OK; k++) {
         const int nb = b ^ 1;
-        r = gemm_launch(-1, n, n, n, buf[b], ld[b], A, lda, buf[nb], ld[nb], s);
+        r = sparse ? sparse_step_launch(buf[b], ld[b], n, w.plan, buf[nb], ld[nb], s)
+                   : gemm_launch(-1, n, n, n, buf[b], ld[b], A, lda, buf[nb], ld[nb], s);
         if (r == MPR_OK) r = normalise_launch(n, n, buf[nb], ld[nb], R_out, nullptr, R_out, st, nullptr, s);
         b = nb;
     }
@@ -186,6 +190,7 @@ static mpr_status power_square(const u16 *A, int64_t n, int64_t lda, int64_t e, 
 // ------------------------------------------------------------ period search
 struct PeriodWs {
     uint64_t *row_hash;
+    void *plan;
     int64_t *scal;  // [0] hash, [1] trace, [2] status (int32 in low half), [3..5] compare
     int64_t slots;
     int64_t ld;
@@ -195,13 +200,14 @@ struct PeriodWs {
     size_t fixed;
 };
 
-static PeriodWs carve_period(void *ws, int64_t n, size_t ws_bytes, int64_t slots_req)
+static PeriodWs carve_period(void *ws, int64_t n, size_t ws_bytes, int64_t slots_req, int flags)
 {
     PeriodWs w{};
     w.ld = round_up(n > 0 ? n : 1, 8);
     Carver c(ws);
     w.row_hash = c.take<uint64_t>((size_t)n);
     w.scal = c.take<int64_t>(8);
+    w.plan = (flags & MPR_PERIOD_SPARSE) ? (void *)c.take<char>(sparse_plan_bytes(n)) : nullptr;
     w.fixed = (size_t)round_up((int64_t)c.used, 256);
     w.slot_elems = (size_t)(n * w.ld);
     w.slot_bytes = (size_t)round_up((int64_t)(w.slot_elems * 2), 256) + (size_t)round_up(n * 8, 256);
@@ -357,7 +363,7 @@ extern "C" mpr_status mpr_minplus_gemm_norm(int64_t M, int64_t N, int64_t K, con
 
 extern "C" mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *bytes_host)
 {
-    if (n < 0 || e < 1 || !bytes_host || (schedule != MPR_CHAIN && schedule != MPR_SQUARE)) return MPR_EINVAL;
+    if (n < 0 || e < 1 || !bytes_host || schedule < MPR_CHAIN || schedule > MPR_CHAIN_SPARSE) return MPR_EINVAL;
     *bytes_host = carve_power(nullptr, n, schedule).bytes;
     return MPR_OK;
 }
@@ -366,7 +372,7 @@ extern "C" mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t ld
                                         uint16_t *N_out, int64_t ldo, int64_t *R_out, void *ws, size_t ws_bytes,
                                         int32_t *d_status, mpr_stream stream)
 {
-    if (n < 0 || e < 1 || (schedule != MPR_CHAIN && schedule != MPR_SQUARE)) return MPR_EINVAL;
+    if (n < 0 || e < 1 || schedule < MPR_CHAIN || schedule > MPR_CHAIN_SPARSE) return MPR_EINVAL;
     if (n && (!A || !N_out || !R_out)) return MPR_EINVAL;
     if (!ld_ok(lda, n) || !ld_ok(ldo, n)) return MPR_EINVAL;
     if (n == 0) return MPR_OK;
@@ -376,8 +382,8 @@ extern "C" mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t ld
     if (r != MPR_OK) return r;
     hipStream_t s = as_stream(stream);
     if ((r = validate_launch(A, n, n, lda, d_status, s)) != MPR_OK) return r;
-    return schedule == MPR_CHAIN ? power_chain(A, n, lda, e, N_out, ldo, R_out, w, d_status, s)
-                                 : power_square(A, n, lda, e, N_out, ldo, R_out, w, d_status, s);
+    if (schedule == MPR_SQUARE) return power_square(A, n, lda, e, N_out, ldo, R_out, w, d_status, s);
+    return power_chain(A, n, lda, e, N_out, ldo, R_out, w, d_status, s, schedule == MPR_CHAIN_SPARSE);
 }
 
 extern "C" mpr_status mpr_trace_min(const uint16_t *N, int64_t n, int64_t ld, const int64_t *R, int64_t *d_gamma,
@@ -399,20 +405,27 @@ extern "C" mpr_status mpr_trace_of_product(const uint16_t *X, const int64_t *RX,
     return trace_product_launch(X, RX, Y, RY, n, ld, d_gamma, as_stream(stream));
 }
 
-extern "C" mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_host)
+extern "C" mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host)
 {
-    if (n < 0 || slots < 2 || !bytes_host) return MPR_EINVAL;
-    PeriodWs w = carve_period(nullptr, n, 0, slots);
+    if (n < 0 || slots < 2 || !bytes_host || (flags & ~MPR_PERIOD_SPARSE)) return MPR_EINVAL;
+    PeriodWs w = carve_period(nullptr, n, 0, slots, flags);
     *bytes_host = w.fixed + (size_t)slots * w.slot_bytes;
     return MPR_OK;
 }
 
-extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int64_t *mu_host,
-                                      int64_t *lam_host, int64_t *c_host, int64_t *traces_host, void *ws,
-                                      size_t ws_bytes, mpr_stream stream)
+extern "C" mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_host)
+{
+    return mpr_period_workspace_size_ex(n, slots, 0, bytes_host);
+}
+
+extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int flags,
+                                         int64_t *mu_host, int64_t *lam_host, int64_t *c_host, int64_t *traces_host,
+                                         void *ws, size_t ws_bytes, mpr_stream stream)
 {
     if (n < 1 || kmax < 1 || !A || !mu_host || !lam_host || !c_host || !ld_ok(lda, n)) return MPR_EINVAL;
-    PeriodWs w = carve_period(ws, n, ws_bytes, 0);
+    if (flags & ~MPR_PERIOD_SPARSE) return MPR_EINVAL;
+    const bool sparse = (flags & MPR_PERIOD_SPARSE) != 0;
+    PeriodWs w = carve_period(ws, n, ws_bytes, 0, flags);
     if (!ws || w.slots < 2) return MPR_ENOMEM;
     mpr_status r = ensure_init();
     if (r != MPR_OK) return r;
@@ -420,6 +433,7 @@ extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda,
     int32_t *st = (int32_t *)&w.scal[2];
     if ((r = fill_i32_launch(st, 2, 0, s)) != MPR_OK) return r;
     if ((r = validate_launch(A, n, n, lda, st, s)) != MPR_OK) return r;
+    if (sparse && (r = sparse_plan_launch(A, n, lda, w.plan, s)) != MPR_OK) return r;
     if (traces_host) traces_host[0] = MPR_ROW_NONE;
 
     // Power k lives in slot (k - 1) % slots (a ring), so a repeat of the class
@@ -436,7 +450,8 @@ extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda,
             r = copy_launch(A, lda, Nk, w.ld, n, n, s);
             if (r == MPR_OK) r = normalise_launch(n, n, Nk, w.ld, nullptr, nullptr, Rk, st, w.row_hash, s);
         } else {
-            r = gemm_launch(-1, n, n, n, slot_N(w, prev_slot), w.ld, A, lda, Nk, w.ld, s);
+            r = sparse ? sparse_step_launch(slot_N(w, prev_slot), w.ld, n, w.plan, Nk, w.ld, s)
+                       : gemm_launch(-1, n, n, n, slot_N(w, prev_slot), w.ld, A, lda, Nk, w.ld, s);
             if (r == MPR_OK)
                 r = normalise_launch(n, n, Nk, w.ld, slot_R(w, prev_slot), nullptr, Rk, st, w.row_hash, s);
         }
@@ -505,4 +520,11 @@ extern "C" mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, con
         numer_host[k % lam] = lam * traces_host[k] - c * k;
     }
     return MPR_OK;
+}
+
+extern "C" mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int64_t *mu_host,
+                                      int64_t *lam_host, int64_t *c_host, int64_t *traces_host, void *ws,
+                                      size_t ws_bytes, mpr_stream stream)
+{
+    return mpr_find_period_ex(A, n, lda, kmax, 0, mu_host, lam_host, c_host, traces_host, ws, ws_bytes, stream);
 }

@@ -15,6 +15,35 @@ constexpr u16 INF16 = 0xFFFF;
 constexpr u16 FMAX16 = 0x7FFF;
 constexpr int64_t ROW_NONE = INT64_MAX;
 
+// Device memory the kernels read and write is global memory; pointers that
+// reach a kernel through a descriptor are generic, so accesses cast them to
+// the global address space explicitly (global, not flat, instructions).
+typedef __attribute__((address_space(1))) u16 gu16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
+template <class X>
+__device__ __forceinline__ __attribute__((address_space(1))) X *glob(X *p)
+{
+    return (__attribute__((address_space(1))) X *)p;
+}
+template <class X>
+__device__ __forceinline__ const __attribute__((address_space(1))) X *glob(const X *p)
+{
+    return (const __attribute__((address_space(1))) X *)p;
+}
+
+// 16-byte global load / store through the global address space.
+__device__ __forceinline__ uint4 gload16(const gu16 *p)
+{
+    const u32x4 v = *(const gu32x4 *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore16(gu16 *p, const uint4 &v)
+{
+    u32x4 w = {v.x, v.y, v.z, v.w};
+    *(gu32x4 *)p = w;
+}
+
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
@@ -81,6 +110,11 @@ int device_cu_count();
 mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda,
                        const u16 *B, int64_t ldb, u16 *C, int64_t ldc, hipStream_t s);
 int pick_config(int64_t M, int64_t N, int64_t K);
+
+// sparse.hip
+size_t sparse_plan_bytes(int64_t n);
+mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hipStream_t s);
+mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s);
 
 // rowops.hip
 mpr_status validate_launch(const u16 *X, int64_t rows, int64_t cols, int64_t ld, int32_t *st, hipStream_t s);

@@ -1,7 +1,8 @@
 // serve.hip -- a continuous-batching query engine for gamma_R(P_m x C_n).
 //
 // For each m the engine keeps a "ladder" of canonical powers resident in
-// HBM: baby steps A^1 .. A^B (a chain) and giant steps A^B, A^2B, ..., and
+// HBM: baby steps A^1 .. A^B (a chain over the compressed rows of the sparse
+// transfer matrix) and giant steps A^B, A^2B, ... (dense products), and
 // answers n = B*i + j (1 <= j <= B) as the trace of A^(B i) (x) A^j, i.e.
 // one HBM-bound trace-of-product pass per query (Corollary 7; the product
 // is never formed).  n <= B is read off the baby traces computed once at
@@ -167,11 +168,12 @@ static size_t ladder_bytes(int m, int B, int G, int64_t *n_out, int64_t *ld_out)
 {
     const int64_t n = transfer_size(m), ld = round_up(n, 8);
     const size_t mat = (size_t)round_up(n * ld * 2, 256), vec = (size_t)round_up(n * 8, 256);
-    // A, B babies, G-1 further giants, one folded operand; then the scalars
+    // A, B babies, G-1 further giants, one folded operand; the scalars; the
+    // compressed-K plan of A used by the baby chain
     const size_t count = 1 + (size_t)B + (size_t)(G > 1 ? G - 1 : 0) + 1;
     if (n_out) *n_out = n;
     if (ld_out) *ld_out = ld;
-    return count * (mat + vec) + (size_t)round_up((int64_t)(B + 8) * 8, 256);
+    return count * (mat + vec) + (size_t)round_up((int64_t)(B + 8) * 8, 256) + sparse_plan_bytes(n);
 }
 
 static int giant_count(const mpr_server_options &o) { return (int)((o.max_n - 1) / o.baby); }
@@ -208,6 +210,8 @@ static mpr_status start_build(Server &S, Ladder &L)
     u16 *Bp = take_mat();
     (void)take_vec();
     int64_t *scal = (int64_t *)p;  // [0] s of the fold, [1..B] traces, then the status word
+    p += round_up((int64_t)(B + 8) * 8, 256);
+    void *plan = p;
     L.trace_dev = scal + 1;
     L.status_dev = (int32_t *)(scal + 2 + B);
     hipStream_t s = S.bstream;
@@ -215,8 +219,10 @@ static mpr_status start_build(Server &S, Ladder &L)
     if (e == MPR_OK) e = transfer_launch(L.m, A, ld, s);
     if (e == MPR_OK) e = copy_launch(A, ld, L.Nb[1], ld, n, n, s);
     if (e == MPR_OK) e = normalise_launch(n, n, L.Nb[1], ld, nullptr, nullptr, L.Rb[1], L.status_dev, nullptr, s);
+    // baby steps by the compressed-K chain (A stays sparse; identical results)
+    if (e == MPR_OK && B >= 2) e = sparse_plan_launch(A, n, ld, plan, s);
     for (int j = 2; j <= B && e == MPR_OK; j++) {
-        e = gemm_launch(-1, n, n, n, L.Nb[j - 1], ld, A, ld, L.Nb[j], ld, s);
+        e = sparse_step_launch(L.Nb[j - 1], ld, n, plan, L.Nb[j], ld, s);
         if (e == MPR_OK)
             e = normalise_launch(n, n, L.Nb[j], ld, L.Rb[j - 1], nullptr, L.Rb[j], L.status_dev, nullptr, s);
     }

@@ -1,0 +1,218 @@
+// sparse.hip -- the chain step N_k = N_(k-1) (x) A when A is sparse.
+//
+// A transfer matrix stays sparse (0.5 - 3 % finite for m = 6..9) while its
+// powers are dense, so in the chain A^k = A^(k-1) (x) A only the rows l of A
+// with a finite entry in an output column can contribute to that column.
+// For a block J of BN output columns let L_J be those rows of A; then
+//     C[:, J] = N[:, L_J] (x) A[L_J, J],
+// a dense (min,+) product with inner dimension |L_J| instead of n.  A plan
+// built once per matrix (on the device, no host round trip) stores, per
+// block, the sorted list L_J (padded with row 0 to a multiple of BK) and the
+// packed rows A[L_J, J] (padding rows infinite, so they never win).  The
+// step runs the shared tile routine with the left operand gathered through
+// L_J.  The result is the same product, entry for entry.
+#include <algorithm>
+
+#include "tile.h"
+
+namespace mpr {
+
+using SCfg = TileCfg<64, 64, 32, 4, 8>;  // 128 threads; 64-column blocks
+constexpr int SBN = SCfg::BN;
+constexpr int SBK = SCfg::BK;
+
+// Does row l of A have a finite entry in columns [j0, j0 + SBN)?
+__device__ __forceinline__ bool row_hits_block(const u16 *A, int64_t lda, int64_t l, int64_t j0, int64_t n, bool vec)
+{
+    const gu16 *row = glob(A) + l * lda;
+    for (int64_t j = j0; j < j0 + SBN && j < n; j += 8) {
+        if (vec && j + 8 <= n) {
+            const uint4 v = gload16(row + j);
+            if ((v.x & v.y & v.z & v.w) != 0xFFFFFFFFu) return true;
+        } else {
+            for (int64_t e = j; e < j + 8 && e < n; e++)
+                if (row[e] != 0xFFFF) return true;
+        }
+    }
+    return false;
+}
+
+// counts[J] = |L_J| rounded up to a multiple of SBK.
+__global__ __launch_bounds__(256) void sp_count_kernel(const u16 *A, int64_t lda, int64_t n, int64_t *counts, int vec)
+{
+    __shared__ uint64_t sh[4];
+    const int64_t j0 = (int64_t)blockIdx.x * SBN;
+    uint64_t c = 0;
+    for (int64_t l = threadIdx.x; l < n; l += 256) c += row_hits_block(A, lda, l, j0, n, vec != 0);
+    c = wave_sum_u64(c);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t t = sh[0] + sh[1] + sh[2] + sh[3];
+        counts[blockIdx.x] = (int64_t)((t + SBK - 1) / SBK * SBK);
+    }
+}
+
+// off[J] = sum of counts before J; off[nblk] = total.  One block.
+__global__ __launch_bounds__(1024) void sp_scan_kernel(const int64_t *counts, int64_t nblk, int64_t *off)
+{
+    __shared__ int64_t part[1024];
+    const int64_t per = (nblk + 1023) / 1024;
+    const int64_t b0 = threadIdx.x * per;
+    int64_t s = 0;
+    for (int64_t b = b0; b < b0 + per && b < nblk; b++) s += counts[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; t++) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        off[nblk] = run;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t b = b0; b < b0 + per && b < nblk; b++) {
+        off[b] = run;
+        run += counts[b];
+    }
+}
+
+// Ordered compaction of block J: idx[off[J] + t] = t-th row of L_J and
+// Bp[(off[J] + t) * SBN + c] = A[l][j0 + c]; padding rows are row 0 / infinite.
+__global__ __launch_bounds__(256) void sp_fill_kernel(const u16 *A, int64_t lda, int64_t n, const int64_t *off,
+                                                      int32_t *idx, u16 *Bp, int vec)
+{
+    __shared__ int wsum[4];
+    __shared__ int64_t run;
+    const int64_t J = blockIdx.x, j0 = J * SBN;
+    const int64_t base = off[J], end = off[J + 1];
+    if (threadIdx.x == 0) run = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t l0 = 0; l0 < n; l0 += 256) {
+        const int64_t l = l0 + threadIdx.x;
+        const bool hit = l < n && row_hits_block(A, lda, l, j0, n, vec != 0);
+        const uint64_t ball = __ballot(hit);
+        const int before = __popcll(ball & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[w] = __popcll(ball);
+        __syncthreads();
+        int pre = 0;
+        for (int q = 0; q < w; q++) pre += wsum[q];
+        const int64_t t = base + run + pre + before;
+        if (hit) {
+            idx[t] = (int32_t)l;
+            const gu16 *src = glob(A) + l * lda;
+            gu16 *dst = glob(Bp) + t * SBN;
+            for (int c = 0; c < SBN; c++) dst[c] = (j0 + c < n) ? src[j0 + c] : (u16)0xFFFF;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    // padding up to the multiple of SBK
+    for (int64_t t = base + run + threadIdx.x; t < end; t += 256) {
+        idx[t] = 0;
+        gu16 *dst = glob(Bp) + t * SBN;
+        for (int c = 0; c < SBN; c++) dst[c] = 0xFFFF;
+    }
+}
+
+// One SCfg tile of C = N[:, L_J] (x) A[L_J, J].
+__global__ __launch_bounds__(SCfg::NT) void sp_step_kernel(const u16 *__restrict__ Np, int64_t ldn, int64_t n,
+                                                           const int64_t *__restrict__ off,
+                                                           const int32_t *__restrict__ idx,
+                                                           const u16 *__restrict__ Bp, u16 *__restrict__ C,
+                                                           int64_t ldc, int tiles_m, int nblk, int vec)
+{
+    __shared__ __attribute__((aligned(16))) u16 lds[SCfg::LDS_ELEMS];
+    // same XCD-aware order as the plain product
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    if (t >= tiles_m * nblk) return;
+    constexpr int G = 8;
+    const int width = G * nblk, first = (t / width) * G, gs = min(tiles_m - first, G), w = t % width;
+    const int tm = first + w % gs, J = w / gs;
+    const int64_t m0 = (int64_t)tm * SCfg::BM, n0 = (int64_t)J * SBN;
+    const int64_t kbeg = off[J], K = off[J + 1] - kbeg;
+    const gu16 *gN = glob(Np);
+    const __attribute__((address_space(1))) int32_t *gi = glob(idx) + kbeg;
+    const gu16 *gB = glob(Bp) + kbeg * SBN;
+    TileAcc<SCfg> acc;
+    tile_mainloop_with<SCfg>(
+        K / SBK,
+        [&](int64_t k0, int row, int kc) {
+            const int64_t r = m0 + row;
+            if (r >= n) return make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+            const gu16 *nr = gN + r * ldn;
+            uint32_t wv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t lo = nr[gi[k0 + kc + 2 * q]], hi = nr[gi[k0 + kc + 2 * q + 1]];
+                wv[q] = lo | (hi << 16);
+            }
+            return make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        },
+        [&](int64_t k0, int kr, int jc) { return gload16(gB + (k0 + kr) * SBN + jc); }, lds, acc);
+    tile_store<SCfg>(C, ldc, n, n, m0, n0, vec != 0, acc);
+}
+
+// ------------------------------------------------------------ host side
+size_t sparse_plan_bytes(int64_t n)
+{
+    const int64_t nblk = (n + SBN - 1) / SBN;
+    const int64_t rows = nblk * round_up(n, SBK);  // bound on sum of padded |L_J|
+    return (size_t)round_up((nblk + 1) * 8, 256) * 2 + (size_t)round_up(rows * 4, 256) +
+           (size_t)round_up(rows * SBN * 2, 256) + 256;
+}
+
+struct SparsePlan {
+    int64_t nblk;
+    int64_t *counts, *off;
+    int32_t *idx;
+    u16 *Bp;
+};
+
+static SparsePlan carve_plan(void *ws, int64_t n)
+{
+    SparsePlan p;
+    p.nblk = (n + SBN - 1) / SBN;
+    const int64_t rows = p.nblk * round_up(n, SBK);
+    char *c = (char *)ws;
+    p.counts = (int64_t *)c;
+    c += round_up((p.nblk + 1) * 8, 256);
+    p.off = (int64_t *)c;
+    c += round_up((p.nblk + 1) * 8, 256);
+    p.idx = (int32_t *)c;
+    c += round_up(rows * 4, 256);
+    p.Bp = (u16 *)c;
+    return p;
+}
+
+mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hipStream_t s)
+{
+    SparsePlan p = carve_plan(ws, n);
+    const int vec = aligned16(A) && lda % 8 == 0;
+    hipLaunchKernelGGL(sp_count_kernel, dim3((unsigned)p.nblk), dim3(256), 0, s, A, lda, n, p.counts, vec);
+    hipLaunchKernelGGL(sp_scan_kernel, dim3(1), dim3(1024), 0, s, (const int64_t *)p.counts, p.nblk, p.off);
+    hipLaunchKernelGGL(sp_fill_kernel, dim3((unsigned)p.nblk), dim3(256), 0, s, A, lda, n, (const int64_t *)p.off,
+                       p.idx, p.Bp, vec);
+    return check_launch();
+}
+
+mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s)
+{
+    SparsePlan p = carve_plan(ws, n);
+    const int64_t tiles_m = (n + SCfg::BM - 1) / SCfg::BM;
+    const int64_t tiles = tiles_m * p.nblk;
+    if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
+    const int vec = aligned16(C) && ldc % 8 == 0;
+    hipLaunchKernelGGL(sp_step_kernel, dim3((unsigned)round_up(tiles, 8)), dim3(SCfg::NT), 0, s, Np, ldn, n,
+                       (const int64_t *)p.off, (const int32_t *)p.idx, (const u16 *)p.Bp, C, ldc, (int)tiles_m,
+                       (int)p.nblk, vec);
+    return check_launch();
+}
+
+}  // namespace mpr

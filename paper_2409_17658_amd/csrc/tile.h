@@ -49,13 +49,14 @@ struct TileCfg {
 __device__ __forceinline__ uint4 load8(const u16 *__restrict__ base, int64_t ld, int64_t row, int64_t col,
                                        int64_t rows, int64_t cols, bool vec)
 {
-    if (vec && row < rows && col + 8 <= cols) return *(const uint4 *)(base + row * ld + col);
+    const gu16 *g = glob(base);
+    if (vec && row < rows && col + 8 <= cols) return gload16(g + row * ld + col);
     uint32_t w[4];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int64_t c0 = col + 2 * q;
-        const uint32_t lo = (row < rows && c0 < cols) ? base[row * ld + c0] : 0xFFFFu;
-        const uint32_t hi = (row < rows && c0 + 1 < cols) ? base[row * ld + c0 + 1] : 0xFFFFu;
+        const uint32_t lo = (row < rows && c0 < cols) ? g[row * ld + c0] : 0xFFFFu;
+        const uint32_t hi = (row < rows && c0 + 1 < cols) ? g[row * ld + c0 + 1] : 0xFFFFu;
         w[q] = lo | (hi << 16);
     }
     return make_uint4(w[0], w[1], w[2], w[3]);
@@ -66,12 +67,14 @@ struct TileAcc {
     u16x2 v[T::TM][T::NACC];
 };
 
-// The k loop of one BM x BN block with top-left corner (m0, n0).
-template <class T>
-__device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t lda,
-                                              const u16 *__restrict__ B, int64_t ldb,
-                                              int64_t M, int64_t N, int64_t K, int64_t m0, int64_t n0,
-                                              bool vec, u16 *lds, TileAcc<T> &acc)
+// The k loop of one BM x BN block.  `aload(k0, row, kc)` returns the 8
+// A-operand values of block row `row` at k = k0 + kc .. k0 + kc + 7 and
+// `bload(k0, kr, jc)` the 8 B-operand values of k = k0 + kr at block columns
+// jc .. jc + 7 (infinity outside the problem); nk is the number of BK-deep
+// slices.  The plain product reads both operands directly; the compressed-K
+// chain step gathers A's columns through an index list.
+template <class T, class ALoad, class BLoad>
+__device__ __forceinline__ void tile_mainloop_with(int64_t nk, ALoad aload, BLoad bload, u16 *lds, TileAcc<T> &acc)
 {
     const int tid = threadIdx.x;
     const int tx = tid % T::TX, ty = tid / T::TX;
@@ -83,7 +86,6 @@ __device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t
 #pragma unroll
         for (int c = 0; c < T::NACC; c++) acc.v[r][c] = (u16x2){0xFFFF, 0xFFFF};
 
-    const int64_t nk = (K + T::BK - 1) / T::BK;
     if (nk == 0) return;
 
     uint4 ra[T::A_CPT], rb[T::B_CPT];
@@ -92,18 +94,12 @@ __device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t
 #pragma unroll
         for (int q = 0; q < T::A_CPT; q++) {
             const int c = tid + q * T::NT;
-            if (T::A_CH % T::NT == 0 || c < T::A_CH) {
-                const int row = c / (T::BK / 8), kc = (c % (T::BK / 8)) * 8;
-                ra[q] = load8(A, lda, m0 + row, k0 + kc, M, K, vec);
-            }
+            if (T::A_CH % T::NT == 0 || c < T::A_CH) ra[q] = aload(k0, c / (T::BK / 8), (c % (T::BK / 8)) * 8);
         }
 #pragma unroll
         for (int q = 0; q < T::B_CPT; q++) {
             const int c = tid + q * T::NT;
-            if (T::B_CH % T::NT == 0 || c < T::B_CH) {
-                const int kr = c / (T::BN / 8), jc = (c % (T::BN / 8)) * 8;
-                rb[q] = load8(B, ldb, k0 + kr, n0 + jc, K, N, vec);
-            }
+            if (T::B_CH % T::NT == 0 || c < T::B_CH) rb[q] = bload(k0, c / (T::BN / 8), (c % (T::BN / 8)) * 8);
         }
     };
     auto sstore = [&](int stage) {
@@ -124,7 +120,6 @@ __device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t
             }
         }
     };
-
     gload(0);
     sstore(0);
     __syncthreads();
@@ -173,6 +168,20 @@ __device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t
     }
 }
 
+
+// The plain product's k loop: A is M x K (lda), B is K x N (ldb), block at (m0, n0).
+template <class T>
+__device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t lda,
+                                              const u16 *__restrict__ B, int64_t ldb,
+                                              int64_t M, int64_t N, int64_t K, int64_t m0, int64_t n0,
+                                              bool vec, u16 *lds, TileAcc<T> &acc)
+{
+    const int64_t nk = (K + T::BK - 1) / T::BK;
+    tile_mainloop_with<T>(
+        nk, [&](int64_t k0, int row, int kc) { return load8(A, lda, m0 + row, k0 + kc, M, K, vec); },
+        [&](int64_t k0, int kr, int jc) { return load8(B, ldb, k0 + kr, n0 + jc, K, N, vec); }, lds, acc);
+}
+
 // Row of the block that accumulator row r of this lane holds.
 template <class T>
 __device__ __forceinline__ int tile_row(int r) { return (int)(threadIdx.x / T::TX) + r * T::TY; }
@@ -193,13 +202,14 @@ __device__ __forceinline__ void tile_store(u16 *__restrict__ C, int64_t ldc, int
             const int64_t col = n0 + tile_col<T>(c8);
             uint4 v = make_uint4(as_u32(acc.v[r][c8 * 4 + 0]), as_u32(acc.v[r][c8 * 4 + 1]),
                                  as_u32(acc.v[r][c8 * 4 + 2]), as_u32(acc.v[r][c8 * 4 + 3]));
+            gu16 *g = glob(C);
             if (vec && col + 8 <= N) {
-                *(uint4 *)(C + row * ldc + col) = v;
+                gstore16(g + row * ldc + col, v);
             } else {
                 const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int e = 0; e < 8; e++)
-                    if (col + e < N) C[row * ldc + col + e] = (u16)(w[e >> 1] >> ((e & 1) * 16));
+                    if (col + e < N) g[row * ldc + col + e] = (u16)(w[e >> 1] >> ((e & 1) * 16));
             }
         }
     }

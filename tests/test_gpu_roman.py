@@ -78,3 +78,35 @@ def test_border_m4_period_and_loss(mpr, paper_values):
     assert (mu, lam, c - lam * shift) == tuple(paper_values["loss_border_m4"]["period"])
     for n in range(10, 301):
         assert tr[n] - n * shift == (12 if n == 11 else n), n
+
+
+@pytest.mark.parametrize("m", [1, 3, 5, 6, 7, 8])
+def test_sparse_chain_digests(mpr, m):
+    """The compressed-K chain (only rows of A reaching each column block)
+    gives the same canonical powers, bit for bit, as the oracle goldens."""
+    g = load(m)
+    A = mpr.build_transfer(m)
+    for k in (1, 2, 3, 26, 64, 300):
+        N, R = mpr.minplus_power(A, k, mpr.CHAIN_SPARSE)
+        assert digest(N, R) == g["digest_sha256"][str(k)], k
+
+
+def test_sparse_period_matches(mpr):
+    for m in (6, 7, 8):
+        g = load(m)
+        A = mpr.build_transfer(m)
+        mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=8, sparse=True)
+        assert [mu, lam, c] == g["period"]
+        assert all(tr[k] == g["trace"][str(k)] for k in range(1, 301))
+
+
+def test_sparse_chain_random_and_edge_blocks(mpr):
+    import oracle as O
+    import synth
+
+    for n, frac, e in [(700, 0.95, 6), (333, 0.99, 9), (129, 0.5, 5), (64, 0.9, 4)]:
+        X = synth.random_matrix(n, n, 77 + n, 0, 40, frac)
+        X[:, 64:128] = 0xFFFF  # an empty column block
+        N, R = mpr.minplus_power(mpr.to_device(X), e, mpr.CHAIN_SPARSE)
+        Nr, Rr = O.power_chain(O.from_u16(X), e)
+        assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), n

@@ -30,7 +30,7 @@ def _small_batch(mpr):
     return chains, mats
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 def test_batch_matches_oracle_and_solo(mpr, cfg):
     print("batch cfg", cfg, flush=True)
     mpr.set_batch_config(cfg)
