@@ -39,6 +39,7 @@ using BCfg1 = TileCfg<32, 128, 32, 4, 8>;   // 128 threads, 32-row panels
 using BCfg2 = TileCfg<128, 128, 32, 8, 8>;  // 256 threads, 128-row panels
 using BCfg3 = TileCfg<64, 128, 32, 8, 8>;   // 128 threads, 64-row panels, 8x8 per lane
 using BCfg4 = TileCfg<64, 256, 32, 8, 16>;  // 128 threads, 64-row panels, 8x16 per lane
+using BCfg5 = TileCfg<64, 64, 32, 4, 8>;    // 128 threads, 64-row panels, 64-column tiles
 
 __device__ __forceinline__ void agent_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void agent_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
@@ -63,10 +64,10 @@ __device__ void panel_normalise(const u16 *src, int64_t lds_, u16 *dst, int64_t 
         const int rr = (int)(t / cpr);
         const int64_t j0 = (t % cpr) * 8;
         const uint32_t r = rmin[rr];
-        const u16 *sp = src + (r0 + rr) * lds_ + j0;
-        u16 *dp = dst + (r0 + rr) * ldd + j0;
+        const gu16 *sp = glob(src) + (r0 + rr) * lds_ + j0;
+        gu16 *dp = glob(dst) + (r0 + rr) * ldd + j0;
         if (vec && j0 + 8 <= n) {
-            const uint4 v = *(const uint4 *)sp;
+            const uint4 v = gload16(sp);
             uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int q = 0; q < 4; q++) {
@@ -74,7 +75,7 @@ __device__ void panel_normalise(const u16 *src, int64_t lds_, u16 *dst, int64_t 
                 over |= (lo != 0xFFFFu && lo > FMAX16) || (hi != 0xFFFFu && hi > FMAX16);
                 w[q] = lo | (hi << 16);
             }
-            *(uint4 *)dp = make_uint4(w[0], w[1], w[2], w[3]);
+            gstore16(dp, make_uint4(w[0], w[1], w[2], w[3]));
         } else {
             for (int64_t j = j0; j < j0 + 8 && j < n; j++) {
                 const uint32_t x = sub_keep_inf(sp[j - j0], r);
@@ -85,7 +86,7 @@ __device__ void panel_normalise(const u16 *src, int64_t lds_, u16 *dst, int64_t 
     }
     for (int rr = threadIdx.x; rr < rows; rr += NT) {
         const uint32_t r = rmin[rr];
-        int64_t &Rv = R[r0 + rr];
+        __attribute__((address_space(1))) int64_t &Rv = glob(R)[r0 + rr];
         if (first)
             Rv = r == 0xFFFFu ? ROW_NONE : (int64_t)r;
         else
@@ -103,10 +104,10 @@ __device__ void panel_rowmin(const u16 *A, int64_t lda, int64_t r0, int rows, in
     for (int64_t t = threadIdx.x; t < total; t += NT) {
         const int rr = (int)(t / cpr);
         const int64_t j0 = (t % cpr) * 8;
-        const u16 *sp = A + (r0 + rr) * lda + j0;
+        const gu16 *sp = glob(A) + (r0 + rr) * lda + j0;
         uint32_t m = 0xFFFFu;
         if (vec && j0 + 8 <= n) {
-            const uint4 v = *(const uint4 *)sp;
+            const uint4 v = gload16(sp);
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int q = 0; q < 4; q++) m = min(m, min(w[q] & 0xFFFFu, w[q] >> 16));
@@ -202,6 +203,7 @@ static const BatchCfgInfo kBatchCfgs[] = {
     {BCfg2::BM, BCfg2::NT, (const void *)batch_kernel<BCfg2>},
     {BCfg3::BM, BCfg3::NT, (const void *)batch_kernel<BCfg3>},
     {BCfg4::BM, BCfg4::NT, (const void *)batch_kernel<BCfg4>},
+    {BCfg5::BM, BCfg5::NT, (const void *)batch_kernel<BCfg5>},
 };
 static constexpr int kNumBatchCfgs = (int)(sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]));
 
