@@ -10,6 +10,7 @@
 // so the grid always drains.  Per step, a panel computes its BM x n slice of
 // the raw product column tile by column tile (the shared tile routine),
 // keeps the running row minima in LDS, then rewrites the slice normalised.
+// Only workgroup barriers separate the phases: no data crosses workgroups.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -41,8 +42,11 @@ using BCfg3 = TileCfg<64, 128, 32, 8, 8>;   // 128 threads, 64-row panels, 8x8 p
 using BCfg4 = TileCfg<64, 256, 32, 8, 16>;  // 128 threads, 64-row panels, 8x16 per lane
 using BCfg5 = TileCfg<64, 64, 32, 4, 8>;    // 128 threads, 64-row panels, 64-column tiles
 
-__device__ __forceinline__ void agent_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void agent_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// A panel's global writes are read back only by the workgroup that wrote
+// them (all its waves run on one CU and share its L1 and its XCD's L2), so a
+// workgroup barrier -- a workgroup-scope release/acquire -- orders them.  An
+// agent-scope fence would write back and invalidate the whole L2 of the XCD
+// on every step.
 
 // Rewrites rows [r0, r0+rows) of src (raw values) into dst, subtracting the
 // row minima in rmin[] (infinity stays) and adding them to R (or setting R
@@ -151,9 +155,7 @@ __global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict
         panel_normalise<T::NT>(c.A, c.lda, buf[b], ld[b], r0, rows, n, rmin, c.R_out, true, vec, st);
 
         for (int64_t k = 2; k <= c.e; k++) {
-            agent_release();
             __syncthreads();
-            agent_acquire();
             const int nb = b ^ 1;
             for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
             // (visibility of rmin is covered by the barriers inside the tile loop)
@@ -179,13 +181,10 @@ __global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict
                     if (threadIdx.x % T::TX == 0) atomicMin(&rmin[tile_row<T>(r)], m);
                 }
             }
-            agent_release();
             __syncthreads();
-            agent_acquire();
             panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, vec, st);
             b = nb;
         }
-        agent_release();
         __syncthreads();
     }
 }
