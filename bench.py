@@ -125,18 +125,24 @@ def bench_gemm(args, mpr, torch):
     peak = valu_peak_gpairs(cus)
     kern_avg = float(np.mean(gemm_ms))
     achieved = pairs / (kern_avg * 1e-3) / 1e9
-    traffic = load_traffic(args.traffic_json)
+    ran_cfg = cfg if cfg >= 0 else mpr.gemm_pick_config(n, n, n)
+    info = mpr.gemm_config_info(ran_cfg)
+    traffic = load_traffic(args.traffic_json, ran_cfg)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "G pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
         "data": "synthetic (SplitMix64 seeds 1, 2; uniform [0,15], 30% infinity)",
         "config": {"workload": "minplus chain step N=16384 uint16 (product + row-min normalisation + trace)",
-                   "n": n, "tile_config": cfg if cfg >= 0 else "table"},
+                   "n": n, "tile_config": ran_cfg,
+                   "tile": "%dx%d, %dx%d per lane, %d threads" % (info["bm"], info["bn"], info["tm"], info["tn"],
+                                                               info["threads"])},
         "pct_valu_peak": round(100.0 * value / peak, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "G pairs/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": "gemm_kernel", "kernel_avg_ms": round(kern_avg, 3)},
+                     "kernel": "gemm_kernel<%d,%d,%d,%d,%d>" % (info["bm"], info["bn"], info["bk"], info["tm"],
+                                                                info["tn"]),
+                     "kernel_avg_ms": round(kern_avg, 3)},
         "input_gen_s": round(gen_s, 1),
     }
     if not args.skip_cpu_baseline:
@@ -156,14 +162,17 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(path):
+def load_traffic(path, cfg: int):
+    """HBM bytes per launch of product configuration cfg at N = 16384, from
+    the copy-calibrated counter runs, if they were taken on these sources."""
     if not path or not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha") != kernel_source_digest():
         return None
-    return t.get("bytes_per_launch")
+    rec = t.get("configs", {}).get(str(cfg))
+    return rec.get("bytes_per_launch") if rec else None
 
 
 def copy_calibration(torch, nbytes=1 << 30):

@@ -326,7 +326,9 @@ typedef struct {
  * requests that do not fit wait).  *server_host receives an opaque handle. */
 mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host);
 /* Queues gamma_R(P_m x C_n); non-blocking and thread-safe.  Requests with
- * m outside 1..11 or n outside 3..max_n complete with MPR_EINVAL. */
+ * m outside 1..11 or n outside 3..max_n complete with MPR_EINVAL, those whose
+ * ladder is larger than the whole budget with MPR_ENOMEM; a ladder whose
+ * build fails completes its requests with the build's status. */
 mpr_status mpr_server_submit(void *server, int m, int64_t n, int64_t tag);
 /* Moves up to capacity finished requests into out_host (host array),
  * waiting up to wait_ms for the first one.  *count_host = number moved. */
@@ -350,6 +352,8 @@ int mpr_gemm_config_count(void);
 /* Describes configuration cfg: tile rows, columns, k depth, per-lane
  * rows/columns and threads per workgroup (host ints, any may be NULL). */
 mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads);
+/* The configuration the tile table gives an M x N x K product (cfg = -1). */
+int mpr_gemm_pick_config(int64_t M, int64_t N, int64_t K);
 /* Installs the size -> configuration table used when cfg = -1: entry t
  * applies to problems whose largest dimension is <= max_dim_host[t]
  * (ascending); larger problems use the last entry.  Copies the arrays. */

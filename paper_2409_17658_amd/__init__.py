@@ -114,6 +114,7 @@ _SIGS = {
     "mpr_gemm_config_count": (_I, []),
     "mpr_gemm_config_info": (_I, [_I, _P, _P, _P, _P, _P, _P]),
     "mpr_set_tile_table": (_I, [_P, _P, _I]),
+    "mpr_gemm_pick_config": (_I, [_I64, _I64, _I64]),
     "mpr_autotune_gemm": (_I, [_I64, _I, _P, _P, _P]),
 }
 
@@ -452,6 +453,10 @@ def gemm_config_info(cfg: int):
     v = [ctypes.c_int() for _ in range(6)]
     _ok(lib().mpr_gemm_config_info(cfg, *[ctypes.byref(x) for x in v]), "mpr_gemm_config_info")
     return dict(zip(["bm", "bn", "bk", "tm", "tn", "threads"], [x.value for x in v]))
+
+
+def gemm_pick_config(M: int, N: int, K: int) -> int:
+    return lib().mpr_gemm_pick_config(M, N, K)
 
 
 def set_tile_table(table):

@@ -122,8 +122,16 @@ __device__ void panel_rowmin(const u16 *A, int64_t lda, int64_t r0, int rows, in
     }
 }
 
+// Register budget: the 4x8-per-lane configurations are held to 128 VGPRs
+// (4 waves per SIMD), the larger tiles to 256.
 template <class T>
-__global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict__ chains,
+struct BatchWaves {
+    static constexpr int value = (T::TM * T::TN <= 32) ? 4 : 2;
+};
+
+template <class T>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<T>::value)))
+void batch_kernel(const DevChain *__restrict__ chains,
                                                       const BatchItem *__restrict__ items, int n_items,
                                                       int *counter, int32_t *st)
 {
@@ -159,12 +167,62 @@ __global__ __launch_bounds__(T::NT) void batch_kernel(const DevChain *__restrict
             const int nb = b ^ 1;
             for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
             // (visibility of rmin is covered by the barriers inside the tile loop)
-            for (int64_t n0 = 0; n0 < n; n0 += T::BN) {
+            // 32-bit offsets: n <= 32768 and leading dimensions <= 65528.
+            const gu16 *Lp = glob(buf[b]) + r0 * ld[b];
+            gu16 *Op = glob(buf[nb]) + r0 * ld[nb];
+            const gu16 *Ap = glob(c.A);
+            const int ldl = (int)ld[b], ldo = (int)ld[nb], lda = (int)c.lda, nn = (int)n;
+            for (int n0 = 0; n0 < nn; n0 += T::BN) {
                 TileAcc<T> acc;
-                // Left operand: rows r0.. of the previous power; the panel's
-                // rows beyond `rows` read as infinity through the M bound.
-                tile_mainloop<T>(buf[b] + r0 * ld[b], ld[b], c.A, c.lda, rows, n, n, 0, n0, vec, lds, acc);
-                tile_store<T>(buf[nb] + r0 * ld[nb], ld[nb], rows, n, 0, n0, vec, acc);
+                // Left operand: rows r0.. of the previous power (rows beyond
+                // `rows` read as infinity); right operand: A.
+                tile_mainloop_with<T>(
+                    (nn + T::BK - 1) / T::BK,
+                    [&](int64_t k0, int row, int kc) {
+                        const int k = (int)k0 + kc;
+                        if (vec && row < rows && k + 8 <= nn) return gload16(Lp + (row * ldl + k));
+                        uint32_t w[4];
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            const uint32_t lo = (row < rows && k + 2 * q < nn) ? Lp[row * ldl + k + 2 * q] : 0xFFFFu;
+                            const uint32_t hi =
+                                (row < rows && k + 2 * q + 1 < nn) ? Lp[row * ldl + k + 2 * q + 1] : 0xFFFFu;
+                            w[q] = lo | (hi << 16);
+                        }
+                        return make_uint4(w[0], w[1], w[2], w[3]);
+                    },
+                    [&](int64_t k0, int kr, int jc) {
+                        const int k = (int)k0 + kr, j = n0 + jc;
+                        if (vec && k < nn && j + 8 <= nn) return gload16(Ap + (k * lda + j));
+                        uint32_t w[4];
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            const uint32_t lo = (k < nn && j + 2 * q < nn) ? Ap[k * lda + j + 2 * q] : 0xFFFFu;
+                            const uint32_t hi = (k < nn && j + 2 * q + 1 < nn) ? Ap[k * lda + j + 2 * q + 1] : 0xFFFFu;
+                            w[q] = lo | (hi << 16);
+                        }
+                        return make_uint4(w[0], w[1], w[2], w[3]);
+                    },
+                    lds, acc);
+#pragma unroll
+                for (int r = 0; r < T::TM; r++) {
+                    const int row = tile_row<T>(r);
+                    if (row >= rows) continue;
+#pragma unroll
+                    for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                        const int col = n0 + tile_col<T>(c8);
+                        const uint4 v = make_uint4(as_u32(acc.v[r][c8 * 4 + 0]), as_u32(acc.v[r][c8 * 4 + 1]),
+                                                   as_u32(acc.v[r][c8 * 4 + 2]), as_u32(acc.v[r][c8 * 4 + 3]));
+                        if (vec && col + 8 <= nn) {
+                            gstore16(Op + (row * ldo + col), v);
+                        } else {
+                            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                            for (int e = 0; e < 8; e++)
+                                if (col + e < nn) Op[row * ldo + col + e] = (u16)(w[e >> 1] >> ((e & 1) * 16));
+                        }
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < T::TM; r++) {
                     uint32_t m = 0xFFFFu;
@@ -323,9 +381,9 @@ static mpr_status check_descs(const mpr_chain_desc *d, int count)
 {
     if (count < 0 || (count && !d)) return MPR_EINVAL;
     for (int i = 0; i < count; i++) {
-        if (d[i].n < 1 || d[i].n > (1 << 30) || d[i].e < 1) return MPR_EINVAL;
+        if (d[i].n < 1 || d[i].n > 32768 || d[i].e < 1) return MPR_EINVAL;
         if (!d[i].A || !d[i].N_out || !d[i].R_out) return MPR_EINVAL;
-        if (d[i].lda < d[i].n || d[i].ldo < d[i].n) return MPR_EINVAL;
+        if (d[i].lda < d[i].n || d[i].ldo < d[i].n || d[i].lda > 65528 || d[i].ldo > 65528) return MPR_EINVAL;
     }
     return MPR_OK;
 }

@@ -134,6 +134,8 @@ extern "C" mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, i
     return MPR_OK;
 }
 
+extern "C" int mpr_gemm_pick_config(int64_t M, int64_t N, int64_t K) { return pick_config(M, N, K); }
+
 extern "C" mpr_status mpr_set_tile_table(const int64_t *max_dim_host, const int *cfg_host, int entries)
 {
     if (entries <= 0 || !max_dim_host || !cfg_host) return MPR_EINVAL;

@@ -109,6 +109,7 @@ struct Ladder {
     int m = 0;
     int64_t n = 0, ld = 0;
     enum State { NONE, BUILDING, READY, FAILED } state = NONE;
+    int fail_status = MPR_OK;  // why a FAILED ladder failed
     void *mem = nullptr;
     size_t bytes = 0;
     std::vector<u16 *> Nb, Ng;        // baby[1..B], giant[1..G] (giant[1] = baby[B])
@@ -288,12 +289,16 @@ static bool admit(Server &S, int m)
     }
     Ladder &L = S.ladders[m];
     L.m = m;
-    if (start_build(S, L) != MPR_OK) {
-        if (L.mem) free_ladder(S, L);
+    const mpr_status e = start_build(S, L);
+    if (e != MPR_OK) {
+        if (L.mem) {
+            (void)hipFree(L.mem);
+            L.mem = nullptr;
+        }
         L.state = Ladder::FAILED;
-        return true;  // the failure is reported to the waiting requests
+        L.fail_status = e;
     }
-    return true;
+    return true;  // building, or failed (reported to the waiting requests)
 }
 
 static void worker_main(Server *Sp)
@@ -337,6 +342,7 @@ static void worker_main(Server *Sp)
                 hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) != hipSuccess)
                 st = MPR_EHIP;
             L.state = st == 0 ? Ladder::READY : Ladder::FAILED;
+            if (st != 0) L.fail_status = st;
             L.build_s = S.now() - L.build_s0;
             L.last_use = S.now();
         }
@@ -344,6 +350,10 @@ static void worker_main(Server *Sp)
         for (auto &r : fresh) {
             if (r.m < 1 || r.m > 11 || r.n < 3 || r.n > S.opt.max_n) {
                 complete(S, r, ROW_NONE, MPR_EINVAL, S.now());
+                continue;
+            }
+            if (ladder_bytes(r.m, B, giant_count(S.opt), nullptr, nullptr) > S.opt.hbm_budget_bytes) {
+                complete(S, r, ROW_NONE, MPR_ENOMEM, S.now());  // could never be admitted
                 continue;
             }
             auto it = S.ladders.find(r.m);
@@ -378,7 +388,7 @@ static void worker_main(Server *Sp)
         for (auto &kv : S.waiting) {
             Ladder &L = S.ladders[kv.first];
             if (L.state == Ladder::FAILED) {
-                for (auto &r : kv.second) complete(S, r, ROW_NONE, MPR_EOVERFLOW, S.now());
+                for (auto &r : kv.second) complete(S, r, ROW_NONE, L.fail_status, S.now());
                 kv.second.clear();
                 continue;
             }

@@ -63,3 +63,4 @@ def test_server_rejects_bad_queries(serve):
         assert S.query(0, 10)["status"] == 1
         r = S.query(1, 50)
         assert r["status"] == 0 and r["gamma"] == math.ceil(2 * 50 / 3)
+        assert S.query(9, 10)["status"] == 2  # its ladder exceeds the 1 GiB budget

@@ -295,3 +295,21 @@ def test_random_matrix_law():
     # counter-based: a sub-block drawn alone equals the same rows of the whole
     B = synth.random_matrix(512, 512, 1, 0, 15, 0.30, chunk_rows=7)
     assert np.array_equal(A, B)
+
+
+def test_entrywise_and_row_restricted_helpers():
+    """minplus_at against the pure-Python triple loop; chain_rows and
+    transfer_rows against whole-matrix computations."""
+    X = O.from_u16(synth.random_matrix(23, 17, 41, 0, 9, 0.3))
+    Y = O.from_u16(synth.random_matrix(17, 29, 42, 0, 9, 0.4))
+    ref = _py_minplus(X.tolist(), Y.tolist())
+    ii, jj = np.meshgrid(np.arange(23), np.arange(29), indexing="ij")
+    got = O.minplus_at(X, Y, ii.ravel(), jj.ravel()).reshape(23, 29)
+    assert got.tolist() == ref
+    A = O.from_u16(synth.random_matrix(60, 60, 43, 0, 20, 0.5))
+    N, R = O.power_chain(A, 7)
+    rows = [0, 13, 59]
+    Nr, Rr = O.chain_rows(A, rows, 7)
+    assert np.array_equal(Nr, N[rows]) and np.array_equal(Rr, R[rows])
+    T = O.transfer(5)
+    assert np.array_equal(O.transfer_rows(5, [0, 7, 286]), T[[0, 7, 286]])
