@@ -36,11 +36,15 @@ PEAK_CLOCK_GHZ = 2.4
 LANES = 64
 
 
-def valu_peak_gpairs(cus: int) -> float:
-    """Packed-u16 VALU peak in G pairs/s: a pair is one add and one min, a
-    packed instruction does two of either per lane, one wave64 instruction
-    per SIMD per 4 clocks, 4 SIMDs per CU -> 64 pairs per CU per clock."""
-    return cus * LANES * PEAK_CLOCK_GHZ
+def valu_peak_gpairs(cus: int, arith: str = "u16") -> float:
+    """VALU peak in G pairs/s for the product's instruction mix; a pair is
+    one add and one min.  A CU issues 64 lane-instructions per clock (one
+    wave64 instruction per SIMD per 4 clocks, 4 SIMDs).  u16: v_pk_add_u16 +
+    v_pk_min_u16 give 2 pairs per 2 lane-instructions -> 64 pairs per CU per
+    clock.  f16 form: two v_pk_add_f16 + one v_pk_minimum3_f16 give 4 pairs
+    per 3 lane-instructions -> 85.3 pairs per CU per clock."""
+    per_clock = LANES * (4.0 / 3.0 if arith == "f16" else 1.0)
+    return cus * per_clock * PEAK_CLOCK_GHZ
 
 
 def cpu_baseline_gemm(X, Y, target_s: float = 15.0):
@@ -91,7 +95,7 @@ def bench_gemm(args, mpr, torch):
     sptr = mpr._stream(stream)
     cfg = args.cfg
 
-    def step(b, ev=None):
+    def step(b, ev=None, cfg=cfg):
         src, dst = P[b], P[b ^ 1]
         if ev is not None:
             ev[0].record(stream)
@@ -122,29 +126,50 @@ def bench_gemm(args, mpr, torch):
     pairs = float(n) ** 3
     value = pairs / (ms_step * 1e-3) / 1e9
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    peak = valu_peak_gpairs(cus)
     kern_avg = float(np.mean(gemm_ms))
     achieved = pairs / (kern_avg * 1e-3) / 1e9
     ran_cfg = cfg if cfg >= 0 else mpr.gemm_pick_config(n, n, n)
     info = mpr.gemm_config_info(ran_cfg)
+    peak = valu_peak_gpairs(cus, info["arith"])
     traffic = load_traffic(args.traffic_json, ran_cfg)
+    u16_form = None
+    if info["arith"] != "u16":
+        # the same tile in the uint16 form, against the packed-int16 peak
+        twin = [c for c in range(mpr.gemm_config_count())
+                if {**mpr.gemm_config_info(c), "arith": info["arith"]} == info and c != ran_cfg][0]
+        ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        b = step(b, None, twin)
+        for k in range(args.steps):
+            b = step(b, ev2[k], twin)
+        torch.cuda.synchronize()
+        mpr.check_status(st)
+        t_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev2]))
+        t_ach = pairs / (t_ms * 1e-3) / 1e9
+        t_peak = valu_peak_gpairs(cus, "u16")
+        u16_form = {"tile_config": twin, "kernel_avg_ms": round(t_ms, 3), "achieved": round(t_ach, 1),
+                    "peak": round(t_peak, 1), "frac": round(t_ach / t_peak, 4),
+                    "traffic": load_traffic(args.traffic_json, twin)}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "G pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": info["arith"],
         "data": "synthetic (SplitMix64 seeds 1, 2; uniform [0,15], 30% infinity)",
         "config": {"workload": "minplus chain step N=16384 uint16 (product + row-min normalisation + trace)",
                    "n": n, "tile_config": ran_cfg,
-                   "tile": "%dx%d, %dx%d per lane, %d threads" % (info["bm"], info["bn"], info["tm"], info["tn"],
-                                                               info["threads"])},
+                   "tile": "%dx%d, %dx%d per lane, %d threads, %s arithmetic" % (
+                       info["bm"], info["bn"], info["tm"], info["tn"], info["threads"], info["arith"]),
+                   "storage": "uint16 in and out; products bit-identical across arithmetic forms"},
         "pct_valu_peak": round(100.0 * value / peak, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "G pairs/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": "gemm_kernel<%d,%d,%d,%d,%d>" % (info["bm"], info["bn"], info["bk"], info["tm"],
-                                                                info["tn"]),
+                     "kernel": "gemm_kernel<%d,%d,%d,%d,%d>, %s" % (info["bm"], info["bn"], info["bk"], info["tm"],
+                                                                    info["tn"], info["arith"]),
                      "kernel_avg_ms": round(kern_avg, 3)},
         "input_gen_s": round(gen_s, 1),
     }
+    if u16_form:
+        out["u16_form"] = u16_form
     if not args.skip_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_gemm(X, Y, args.cpu_seconds)
     return out
@@ -305,10 +330,42 @@ def bench_config3(args, mpr, torch):
                     "sparse_period_same": same_per, "gamma_3_300_match_golden": ok}
     tot = sum(299 * float(v["n_states"]) ** 3 for v in per_m.values())
     tt = sum(v["chain_300_s"] for v in per_m.values())
+    if args.with_m9:
+        per_m[9] = bench_m9(mpr, torch)
     return {"metric": "Roman transfer powers to n=300 (m=6,7,8): chain GOPS", "value": round(tot / tt / 1e9, 1),
             "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16", "data": "transfer matrices",
             "config": {"workload": "A(G)^300 by chain and by squaring, period search, gamma_R(3..300)"},
             "per_m": per_m}
+
+
+def bench_m9(mpr, torch):
+    """m = 9 (21909 states), the paper's largest exact case: the 50 powers of
+    its Table 2 / Table 3 run, dense and compressed-K, and the period search;
+    checked against Table 2 and the Section 4.3 closed form."""
+    A = mpr.build_transfer(9)
+    n = A.shape[0]
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {"n_states": n}
+    for name, sched in (("dense", mpr.CHAIN), ("sparse", mpr.CHAIN_SPARSE)):
+        ws = mpr.workspace(mpr.power_workspace_size(n, 50, sched))
+        N = mpr.alloc_matrix(n, n)
+        R = torch.empty(n, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mpr.minplus_power(A, 50, sched, N, R, ws, check=False, d_status=st)
+        torch.cuda.synchronize()
+        out["A50_%s_s" % name] = round(time.perf_counter() - t0, 3)
+        print("m9: A^50 %s %.2f s" % (name, out["A50_%s_s" % name]), file=sys.stderr, flush=True)
+        del ws, N, R
+    mpr.check_status(st)
+    t0 = time.perf_counter()
+    mu, lam, c, tr = mpr.find_period(A, 60, traces=True, slots=8, sparse=True)
+    out["find_period_sparse_s"] = round(time.perf_counter() - t0, 3)
+    out["period"] = [mu, lam, c]
+    out["closed_form_ok"] = all(int(tr[k]) == (4 * k if k % 5 == 0 else 4 * k + 2) for k in range(3, 61))
+    out["dense_gpairs"] = round(49 * float(n) ** 3 / out["A50_dense_s"] / 1e9, 1)
+    out["paper_k80_50_powers_s"] = {"total": 4587, "kernel": 3100}
+    return out
 
 
 # ---------------------------------------------------------------- m = 10
@@ -406,16 +463,18 @@ def bench_config4(args, mpr, torch):
     same = all(torch.equal(N.view(torch.int16), b[0].view(torch.int16)) and torch.equal(R, b[1])
                for (_, _, N, R), b in zip(chains, batched))
     cus = torch.cuda.get_device_properties(0).multi_processor_count
+    binfo = mpr.batch_config_info(best)
     return {"metric": "batched min-plus power chains GOPS (256 chains, one persistent launch in a HIP graph)",
             "value": round(pairs / t_batch / 1e9, 1), "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": "u16", "data": "synthetic (batch_instances seed 4; entries U[0,31], 25% infinity)",
+            "dtype": binfo["arith"], "data": "synthetic (batch_instances seed 4; entries U[0,31], 25% infinity)",
             "config": {"workload": "256 chains, N log-uniform [256,4096], e uniform [8,128]",
-                       "total_pairs": pairs, "batch_config": best,
-                       "panel_rows": mpr.batch_config_info(best)["panel_rows"]},
+                       "total_pairs": pairs, "batch_config": best, "panel_rows": binfo["panel_rows"],
+                       "per_instance_tile_configs": sorted({mpr.gemm_pick_config(d["n"], d["n"], d["n"])
+                                                            for d in inst})},
             "batched_s": round(t_batch, 3), "per_instance_s": round(t_solo, 3),
             "per_instance_gpairs": round(pairs / t_solo / 1e9, 1),
             "speedup_vs_per_instance": round(t_solo / t_batch, 2),
-            "pct_valu_peak": round(100 * pairs / t_batch / 1e9 / valu_peak_gpairs(cus), 2),
+            "pct_valu_peak": round(100 * pairs / t_batch / 1e9 / valu_peak_gpairs(cus, binfo["arith"]), 2),
             "autotune_s": {str(k): round(v, 3) for k, v in tune.items()},
             "batched_equals_per_instance": bool(same), "input_gen_s": round(gen_s, 1)}
 
@@ -472,6 +531,7 @@ def main():
     ap.add_argument("--cfg", type=int, default=-1, help="tile configuration (-1: tile table)")
     ap.add_argument("--workload", default="gemm", choices=["gemm", "config2", "config3", "config4", "serve", "m10"])
     ap.add_argument("--m10-kmax", type=int, default=35)
+    ap.add_argument("--with-m9", type=int, default=1, help="config3: also the m = 9 run")
     ap.add_argument("--m10-sparse", type=int, default=1)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -65,6 +65,16 @@ typedef enum {
                             * reach each block of output columns */
 #define MPR_PERIOD_SPARSE 1 /* mpr_find_period_ex flag: compressed-K chain steps */
 
+/* Arithmetic of a product configuration.  MPR_ARITH_U16: packed uint16
+ * saturating add and min.  MPR_ARITH_F16: the operands' f16 images (a
+ * finite value below 0x800 is its own f16 bit pattern, 0xFFFF is +inf,
+ * larger finite values are clamped to 0x800), two k per packed 3-input
+ * minimum; round-to-nearest is exact below 2048, so every result below
+ * 0x800 or infinite is exact, and a tile holding any other result is
+ * recomputed in uint16.  Both give the same C bit for bit. */
+#define MPR_ARITH_U16 0
+#define MPR_ARITH_F16 1
+
 typedef void *mpr_stream;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -273,10 +283,16 @@ mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream stream);
 mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count,
                            void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
 
+/* Arithmetic (MPR_ARITH_*) of the compressed-K chain steps of
+ * MPR_CHAIN_SPARSE and MPR_PERIOD_SPARSE; MPR_ARITH_F16 by default.  Both
+ * give the same powers bit for bit.  Process-wide setting. */
+mpr_status mpr_set_sparse_arith(int arith);
+
 /* Number of compiled batched-kernel configurations (panel heights). */
 int mpr_batch_config_count(void);
-/* Rows per panel and threads per workgroup of batched configuration cfg. */
-mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads);
+/* Rows per panel, threads per workgroup and arithmetic (MPR_ARITH_*) of
+ * batched configuration cfg (host ints, any may be NULL). */
+mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads, int *arith);
 /* Forces the configuration later mpr_batch_plan calls use (-1 = choose by
  * a longest-first schedule model of the batch).  Process-wide setting. */
 mpr_status mpr_set_batch_config(int cfg);
@@ -350,8 +366,10 @@ mpr_status mpr_server_destroy(void *server);
 /* Number of compiled (min,+) tile configurations. */
 int mpr_gemm_config_count(void);
 /* Describes configuration cfg: tile rows, columns, k depth, per-lane
- * rows/columns and threads per workgroup (host ints, any may be NULL). */
-mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads);
+ * rows/columns, threads per workgroup and arithmetic (MPR_ARITH_*) (host
+ * ints, any may be NULL). */
+mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads,
+                                int *arith);
 /* The configuration the tile table gives an M x N x K product (cfg = -1). */
 int mpr_gemm_pick_config(int64_t M, int64_t N, int64_t K);
 /* Installs the size -> configuration table used when cfg = -1: entry t

@@ -31,6 +31,8 @@ CHAIN = 0
 SQUARE = 1
 CHAIN_SPARSE = 2
 PERIOD_SPARSE = 1
+ARITH_U16 = 0
+ARITH_F16 = 1
 
 _STATUS = {0: "MPR_OK", 1: "MPR_EINVAL", 2: "MPR_ENOMEM", 3: "MPR_EOVERFLOW",
            4: "MPR_ENOTFOUND", 5: "MPR_EHIP", 6: "MPR_EUNSUPPORTED"}
@@ -99,7 +101,8 @@ _SIGS = {
     "mpr_batch_launch": (_I, [_P, _P, _P]),
     "mpr_batch_power": (_I, [_P, _I, _P, _SZ, _P, _P]),
     "mpr_batch_config_count": (_I, []),
-    "mpr_batch_config_info": (_I, [_I, _P, _P]),
+    "mpr_batch_config_info": (_I, [_I, _P, _P, _P]),
+    "mpr_set_sparse_arith": (_I, [_I]),
     "mpr_set_batch_config": (_I, [_I]),
     "mpr_batch_graph_create": (_I, [_P, _P, _P, _P]),
     "mpr_graph_launch": (_I, [_P, _P]),
@@ -112,7 +115,7 @@ _SIGS = {
     "mpr_server_ladder_bytes": (_I64, [_I, _I, _I64]),
     "mpr_server_destroy": (_I, [_P]),
     "mpr_gemm_config_count": (_I, []),
-    "mpr_gemm_config_info": (_I, [_I, _P, _P, _P, _P, _P, _P]),
+    "mpr_gemm_config_info": (_I, [_I, _P, _P, _P, _P, _P, _P, _P]),
     "mpr_set_tile_table": (_I, [_P, _P, _I]),
     "mpr_gemm_pick_config": (_I, [_I64, _I64, _I64]),
     "mpr_autotune_gemm": (_I, [_I64, _I, _P, _P, _P]),
@@ -435,9 +438,15 @@ def batch_config_count() -> int:
 
 
 def batch_config_info(cfg: int):
-    r, t = ctypes.c_int(), ctypes.c_int()
-    _ok(lib().mpr_batch_config_info(cfg, ctypes.byref(r), ctypes.byref(t)), "mpr_batch_config_info")
-    return {"panel_rows": r.value, "threads": t.value}
+    r, t, a = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _ok(lib().mpr_batch_config_info(cfg, ctypes.byref(r), ctypes.byref(t), ctypes.byref(a)),
+        "mpr_batch_config_info")
+    return {"panel_rows": r.value, "threads": t.value, "arith": "f16" if a.value == ARITH_F16 else "u16"}
+
+
+def set_sparse_arith(arith: str):
+    """'f16' (default) or 'u16' for the compressed-K chain steps."""
+    _ok(lib().mpr_set_sparse_arith(ARITH_F16 if arith == "f16" else ARITH_U16), "mpr_set_sparse_arith")
 
 
 def set_batch_config(cfg: int):
@@ -450,9 +459,11 @@ def gemm_config_count() -> int:
 
 
 def gemm_config_info(cfg: int):
-    v = [ctypes.c_int() for _ in range(6)]
+    v = [ctypes.c_int() for _ in range(7)]
     _ok(lib().mpr_gemm_config_info(cfg, *[ctypes.byref(x) for x in v]), "mpr_gemm_config_info")
-    return dict(zip(["bm", "bn", "bk", "tm", "tn", "threads"], [x.value for x in v]))
+    d = dict(zip(["bm", "bn", "bk", "tm", "tn", "threads", "arith"], [x.value for x in v]))
+    d["arith"] = "f16" if d["arith"] == ARITH_F16 else "u16"
+    return d
 
 
 def gemm_pick_config(M: int, N: int, K: int) -> int:

@@ -4,7 +4,6 @@
 // period search of Algorithm 2).
 #include <string.h>
 
-#include <atomic>
 #include <mutex>
 #include <unordered_map>
 #include <vector>

@@ -129,7 +129,7 @@ struct BatchWaves {
     static constexpr int value = (T::TM * T::TN <= 32) ? 4 : 2;
 };
 
-template <class T>
+template <class T, bool H>
 __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<T>::value)))
 void batch_kernel(const DevChain *__restrict__ chains,
                                                       const BatchItem *__restrict__ items, int n_items,
@@ -176,7 +176,7 @@ void batch_kernel(const DevChain *__restrict__ chains,
                 TileAcc<T> acc;
                 // Left operand: rows r0.. of the previous power (rows beyond
                 // `rows` read as infinity); right operand: A.
-                tile_mainloop_with<T>(
+                tile_mainloop_with<T, H>(
                     (nn + T::BK - 1) / T::BK,
                     [&](int64_t k0, int row, int kc) {
                         const int k = (int)k0 + kc;
@@ -251,17 +251,19 @@ __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
 
 // ------------------------------------------------------------ host side
 struct BatchCfgInfo {
-    int bm, nt;
+    int bm, nt, arith;
     const void *kernel;
 };
+// 0..5 compute in uint16, 6..11 are the same tiles in the f16 form (same
+// results bit for bit; see tile.h).
+#define MPR_BCFG(T, H) {T::BM, T::NT, H ? MPR_ARITH_F16 : MPR_ARITH_U16, (const void *)batch_kernel<T, H>}
 static const BatchCfgInfo kBatchCfgs[] = {
-    {BCfg0::BM, BCfg0::NT, (const void *)batch_kernel<BCfg0>},
-    {BCfg1::BM, BCfg1::NT, (const void *)batch_kernel<BCfg1>},
-    {BCfg2::BM, BCfg2::NT, (const void *)batch_kernel<BCfg2>},
-    {BCfg3::BM, BCfg3::NT, (const void *)batch_kernel<BCfg3>},
-    {BCfg4::BM, BCfg4::NT, (const void *)batch_kernel<BCfg4>},
-    {BCfg5::BM, BCfg5::NT, (const void *)batch_kernel<BCfg5>},
+    MPR_BCFG(BCfg0, false), MPR_BCFG(BCfg1, false), MPR_BCFG(BCfg2, false),
+    MPR_BCFG(BCfg3, false), MPR_BCFG(BCfg4, false), MPR_BCFG(BCfg5, false),
+    MPR_BCFG(BCfg0, true),  MPR_BCFG(BCfg1, true),  MPR_BCFG(BCfg2, true),
+    MPR_BCFG(BCfg3, true),  MPR_BCFG(BCfg4, true),  MPR_BCFG(BCfg5, true),
 };
+#undef MPR_BCFG
 static constexpr int kNumBatchCfgs = (int)(sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]));
 
 struct BatchPlan {
@@ -343,9 +345,11 @@ static int choose_batch_cfg(const mpr_chain_desc *d, int count)
                 w.push_back((double)(d[i].e - 1) * (double)std::min<int64_t>(bm, d[i].n - r0) * (double)d[i].n *
                             (double)d[i].n);
         std::sort(w.begin(), w.end(), std::greater<double>());
-        // A worker's speed is the CU's rate shared among its resident workers.
+        // A worker's speed is the CU's rate shared among its resident workers;
+        // the f16 form issues 3 instructions where the uint16 form issues 4.
         const int per_cu = std::max(1, occupancy(c));
-        const double t = lpt_makespan(w, cus * per_cu) * per_cu;
+        const double rate = kBatchCfgs[c].arith == MPR_ARITH_F16 ? 0.75 : 1.0;
+        const double t = lpt_makespan(w, cus * per_cu) * per_cu * rate;
         if (t < best_t) {
             best_t = t;
             best = c;
@@ -362,11 +366,12 @@ using namespace mpr;
 
 extern "C" int mpr_batch_config_count(void) { return kNumBatchCfgs; }
 
-extern "C" mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads)
+extern "C" mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads, int *arith)
 {
     if (cfg < 0 || cfg >= kNumBatchCfgs) return MPR_EINVAL;
     if (panel_rows) *panel_rows = kBatchCfgs[cfg].bm;
     if (threads) *threads = kBatchCfgs[cfg].nt;
+    if (arith) *arith = kBatchCfgs[cfg].arith;
     return MPR_OK;
 }
 

@@ -52,6 +52,26 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(
 __device__ __forceinline__ u16x2 add_sat(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
 __device__ __forceinline__ u16x2 min2(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
 
+// The f16 image of a (min,+) value, used by the f16 form of the tile
+// routine.  A finite uint16 x < 0x800 is, read as an f16 bit pattern, the
+// number x * 2^-24 (subnormals and the first binade share the spacing
+// 2^-24), so sums of such values below 2048 are exact and their bit
+// patterns are the integer sums.  Infinity 0xFFFF becomes +inf (0x7C00);
+// finite values >= 0x800 are clamped to 0x800, which keeps every sum they
+// enter at or above 0x800 (flagged by tile_from_h16) and far from overflow.
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h16x2 as_h16x2(uint32_t v) { return __builtin_bit_cast(h16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(h16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t to_h16(uint32_t x)
+{
+    // Signed, 0xFFFF is -1 and survives min(., 0x800); unsigned, it then
+    // meets 0x7C00 while the clamped finite values pass: two v_pk_min.
+    const i16x2 c = __builtin_elementwise_min(__builtin_bit_cast(i16x2, x), (i16x2){0x800, 0x800});
+    return as_u32(min2(__builtin_bit_cast(u16x2, c), (u16x2){0x7C00, 0x7C00}));
+}
+__device__ __forceinline__ u16 to_h16_1(u16 x) { return x == 0xFFFF ? (u16)0x7C00 : (x < 0x800 ? x : (u16)0x800); }
+
 __device__ __forceinline__ uint32_t comp(const uint4 &v, int q)
 {
     return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;

@@ -37,8 +37,15 @@ __device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm,
     return true;
 }
 
+// Waves per SIMD the register allocation must allow: 4 (<= 128 VGPRs) for
+// tiles of up to 64 outputs per lane, 2 for the larger ones.
 template <class T>
-__global__ __launch_bounds__(T::NT) void gemm_kernel(const u16 *__restrict__ A, int64_t lda,
+struct GemmWaves {
+    static constexpr int value = T::TM * T::TN <= 64 ? 4 : 2;
+};
+
+template <class T, bool H>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value))) void gemm_kernel(const u16 *__restrict__ A, int64_t lda,
                                                      const u16 *__restrict__ B, int64_t ldb,
                                                      u16 *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
                                                      int64_t K, int tiles_m, int tiles_n, int vec)
@@ -48,7 +55,7 @@ __global__ __launch_bounds__(T::NT) void gemm_kernel(const u16 *__restrict__ A, 
     if (!tile_of_block(tiles_m, tiles_n, tm, tn)) return;
     const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
     TileAcc<T> acc;
-    tile_mainloop<T>(A, lda, B, ldb, M, N, K, m0, n0, vec != 0, lds, acc);
+    tile_mainloop<T, H>(A, lda, B, ldb, M, N, K, m0, n0, vec != 0, lds, acc);
     tile_store<T>(C, ldc, M, N, m0, n0, vec != 0, acc);
 }
 
@@ -60,7 +67,7 @@ __global__ void fill_inf_kernel(u16 *C, int64_t ldc, int64_t M, int64_t N)
         C[(t / N) * ldc + t % N] = 0xFFFF;
 }
 
-template <class T>
+template <class T, bool H>
 static mpr_status launch_cfg(int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
                              int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
 {
@@ -69,27 +76,32 @@ static mpr_status launch_cfg(int64_t M, int64_t N, int64_t K, const u16 *A, int6
     if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
     const int64_t blocks = round_up(tiles, 8);
     const bool vec = aligned16(A) && aligned16(B) && aligned16(C) && lda % 8 == 0 && ldb % 8 == 0 && ldc % 8 == 0;
-    hipLaunchKernelGGL(gemm_kernel<T>, dim3((unsigned)blocks), dim3(T::NT), 0, s, A, lda, B, ldb, C, ldc, M, N, K,
+    hipLaunchKernelGGL((gemm_kernel<T, H>), dim3((unsigned)blocks), dim3(T::NT), 0, s, A, lda, B, ldb, C, ldc, M, N, K,
                        (int)tiles_m, (int)tiles_n, vec ? 1 : 0);
     return check_launch();
 }
 
 struct CfgInfo {
-    int bm, bn, bk, tm, tn, nt;
+    int bm, bn, bk, tm, tn, nt, arith;
     mpr_status (*launch)(int64_t, int64_t, int64_t, const u16 *, int64_t, const u16 *, int64_t, u16 *, int64_t,
                          hipStream_t);
 };
 
-#define MPR_CFG(T) {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, launch_cfg<T>}
-static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0), MPR_CFG(Cfg1), MPR_CFG(Cfg2),
-                                MPR_CFG(Cfg3), MPR_CFG(Cfg4), MPR_CFG(Cfg5)};
+// Configurations 0..5 compute in uint16 (MPR_ARITH_U16); 6..11 are the
+// same tiles in the f16 form with the uint16 recomputation of inexact blocks
+// (MPR_ARITH_F16), which gives the same product bit for bit.
+#define MPR_CFG(T, H) {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, H ? MPR_ARITH_F16 : MPR_ARITH_U16, launch_cfg<T, H>}
+static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0, false), MPR_CFG(Cfg1, false), MPR_CFG(Cfg2, false),
+                                MPR_CFG(Cfg3, false), MPR_CFG(Cfg4, false), MPR_CFG(Cfg5, false),
+                                MPR_CFG(Cfg0, true),  MPR_CFG(Cfg1, true),  MPR_CFG(Cfg2, true),
+                                MPR_CFG(Cfg3, true),  MPR_CFG(Cfg4, true),  MPR_CFG(Cfg5, true)};
 #undef MPR_CFG
 static constexpr int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 
 // Size -> configuration table (largest dimension, ascending).  The default
 // is replaced by mpr_set_tile_table with the autotuner's measurements.
 static std::mutex g_table_mu;
-static std::vector<std::pair<int64_t, int>> g_table = {{96, 3}, {1024, 0}, {INT64_MAX, 1}};
+static std::vector<std::pair<int64_t, int>> g_table = {{96, 9}, {1024, 6}, {INT64_MAX, 6}};
 
 int pick_config(int64_t M, int64_t N, int64_t K)
 {
@@ -121,7 +133,8 @@ using namespace mpr;
 
 extern "C" int mpr_gemm_config_count(void) { return kNumCfgs; }
 
-extern "C" mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads)
+extern "C" mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads,
+                                           int *arith)
 {
     if (cfg < 0 || cfg >= kNumCfgs) return MPR_EINVAL;
     const CfgInfo &c = kCfgs[cfg];
@@ -131,6 +144,7 @@ extern "C" mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, i
     if (tm) *tm = c.tm;
     if (tn) *tn = c.tn;
     if (threads) *threads = c.nt;
+    if (arith) *arith = c.arith;
     return MPR_OK;
 }
 

@@ -10,7 +10,7 @@
 //
 // A worker thread owns every HIP call.  Each tick it gathers the requests
 // whose ladder is ready into ONE grouped launch on the query stream (up to
-// kSlots launches in flight), while ladder builds run on a separate build
+// `slots` launches in flight), while ladder builds run on a separate build
 // stream, so queries for warm m keep flowing while a cold m is built.  A
 // ladder is admitted only if its bytes fit the HBM budget; idle ladders are
 // evicted least-recently-used to make room, and requests that do not fit
@@ -21,7 +21,6 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
-#include <list>
 #include <map>
 #include <string>
 #include <mutex>

@@ -120,8 +120,43 @@ __global__ __launch_bounds__(256) void sp_fill_kernel(const u16 *A, int64_t lda,
     }
 }
 
-// One SCfg tile of C = N[:, L_J] (x) A[L_J, J].
-__global__ __launch_bounds__(SCfg::NT) void sp_step_kernel(const u16 *__restrict__ Np, int64_t ldn, int64_t n,
+// Left operand of the compressed-K step: N[m0 + row][L_J[k]] for the BK-deep
+// slice.  Thread t handles k = t % BK (fixed: NT is a multiple of BK), so it
+// reads its index once per slice, and rows t / BK + e * (NT / BK); a wave thus
+// reads 32 consecutive gathered columns (sorted, mostly adjacent) of two rows
+// per instruction, and the values go to LDS one 16-bit store each.
+template <class T>
+struct GatherA {
+    static_assert(T::NT % T::BK == 0, "fixed k per thread");
+    static constexpr int PER = T::BM * T::BK / T::NT;  // values per thread
+    static constexpr int RSTEP = T::NT / T::BK;        // rows between them
+    const gu16 *N;
+    int64_t ldn, n, m0;
+    const __attribute__((address_space(1))) int32_t *idx;
+    uint32_t v[PER];
+    __device__ __forceinline__ void load(int64_t k0)
+    {
+        const int k = (int)(threadIdx.x % T::BK), r0 = (int)(threadIdx.x / T::BK);
+        const int64_t col = idx[k0 + k];
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            const int64_t r = m0 + r0 + e * RSTEP;
+            v[e] = r < n ? (uint32_t)N[r * ldn + col] : 0xFFFFu;
+        }
+    }
+    template <bool H>
+    __device__ __forceinline__ void store(u16 *as) const
+    {
+        const int k = (int)(threadIdx.x % T::BK), r0 = (int)(threadIdx.x / T::BK);
+#pragma unroll
+        for (int e = 0; e < PER; e++)
+            as[(r0 + e * RSTEP) * T::LDA_S + k] = H ? to_h16_1((u16)v[e]) : (u16)v[e];
+    }
+};
+
+// One SCfg tile of C = N[:, L_J] (x) A[L_J, J], in form H (tile.h).
+template <bool H>
+__global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) void sp_step_kernel(const u16 *__restrict__ Np, int64_t ldn, int64_t n,
                                                            const int64_t *__restrict__ off,
                                                            const int32_t *__restrict__ idx,
                                                            const u16 *__restrict__ Bp, u16 *__restrict__ C,
@@ -141,21 +176,9 @@ __global__ __launch_bounds__(SCfg::NT) void sp_step_kernel(const u16 *__restrict
     const __attribute__((address_space(1))) int32_t *gi = glob(idx) + kbeg;
     const gu16 *gB = glob(Bp) + kbeg * SBN;
     TileAcc<SCfg> acc;
-    tile_mainloop_with<SCfg>(
-        K / SBK,
-        [&](int64_t k0, int row, int kc) {
-            const int64_t r = m0 + row;
-            if (r >= n) return make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-            const gu16 *nr = gN + r * ldn;
-            uint32_t wv[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const uint32_t lo = nr[gi[k0 + kc + 2 * q]], hi = nr[gi[k0 + kc + 2 * q + 1]];
-                wv[q] = lo | (hi << 16);
-            }
-            return make_uint4(wv[0], wv[1], wv[2], wv[3]);
-        },
-        [&](int64_t k0, int kr, int jc) { return gload16(gB + (k0 + kr) * SBN + jc); }, lds, acc);
+    GatherA<SCfg> aop{gN, ldn, n, m0, gi, {}};
+    auto bop = chunk_b<SCfg>([&](int64_t k0, int kr, int jc) { return gload16(gB + (k0 + kr) * SBN + jc); });
+    tile_product<SCfg, H>(K / SBK, aop, bop, lds, acc);
     tile_store<SCfg>(C, ldc, n, n, m0, n0, vec != 0, acc);
 }
 
@@ -202,6 +225,8 @@ mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hi
     return check_launch();
 }
 
+static int g_sparse_arith = MPR_ARITH_F16;
+
 mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s)
 {
     SparsePlan p = carve_plan(ws, n);
@@ -209,10 +234,18 @@ mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u
     const int64_t tiles = tiles_m * p.nblk;
     if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
     const int vec = aligned16(C) && ldc % 8 == 0;
-    hipLaunchKernelGGL(sp_step_kernel, dim3((unsigned)round_up(tiles, 8)), dim3(SCfg::NT), 0, s, Np, ldn, n,
+    auto kernel = g_sparse_arith == MPR_ARITH_F16 ? sp_step_kernel<true> : sp_step_kernel<false>;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)round_up(tiles, 8)), dim3(SCfg::NT), 0, s, Np, ldn, n,
                        (const int64_t *)p.off, (const int32_t *)p.idx, (const u16 *)p.Bp, C, ldc, (int)tiles_m,
                        (int)p.nblk, vec);
     return check_launch();
 }
 
 }  // namespace mpr
+
+extern "C" mpr_status mpr_set_sparse_arith(int arith)
+{
+    if (arith != MPR_ARITH_U16 && arith != MPR_ARITH_F16) return MPR_EINVAL;
+    mpr::g_sparse_arith = arith;
+    return MPR_OK;
+}

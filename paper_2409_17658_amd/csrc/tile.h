@@ -14,6 +14,17 @@
 // exact for finite pairs and returns 0xFFFF whenever an operand is
 // infinite, so no branch is needed anywhere in the inner loop; out-of-range
 // rows, columns and k are loaded as infinity and drop out of the minimum.
+//
+// The f16 form (H = true) runs the same loop on the f16 images of the
+// operands (to_h16: small values are their own bit patterns, infinity is
+// +inf), two k at a time: two v_pk_add_f16 and one v_pk_minimum3_f16 per
+// pair of outputs, 3 instructions for 4 (add, min) pairs instead of 4.
+// Round-to-nearest is monotone and exact below 2048, so a result below
+// 0x800 is the exact minimum, +inf means every term had an infinite operand
+// (exactly the uint16 infinity: finite sums never reach 0xFFFF), and any
+// other result means the true minimum is >= 2048; a block that holds such a
+// result recomputes its tile with the uint16 loop (tile_product).  The
+// f16 form thus gives the uint16 product bit for bit on every input.
 #pragma once
 
 #include "common.h"
@@ -67,66 +78,110 @@ struct TileAcc {
     u16x2 v[T::TM][T::NACC];
 };
 
-// The k loop of one BM x BN block.  `aload(k0, row, kc)` returns the 8
-// A-operand values of block row `row` at k = k0 + kc .. k0 + kc + 7 and
-// `bload(k0, kr, jc)` the 8 B-operand values of k = k0 + kr at block columns
-// jc .. jc + 7 (infinity outside the problem); nk is the number of BK-deep
-// slices.  The plain product reads both operands directly; the compressed-K
-// chain step gathers A's columns through an index list.
-template <class T, class ALoad, class BLoad>
-__device__ __forceinline__ void tile_mainloop_with(int64_t nk, ALoad aload, BLoad bload, u16 *lds, TileAcc<T> &acc)
+// 8 staged values as the k loop of form H reads them.
+template <bool H>
+__device__ __forceinline__ uint4 image(const uint4 &v)
+{
+    if constexpr (H) return make_uint4(to_h16(v.x), to_h16(v.y), to_h16(v.z), to_h16(v.w));
+    return v;
+}
+
+// Operand staging.  The k loop asks an operand policy to `load(k0)` the
+// BK-deep slice starting at k0 into registers (issued before the math on the
+// current slice, so its latency is hidden) and later to `store(stage)` it
+// into the LDS stage (`store<H>`, in the representation of form H): A as
+// rows of BK (stride LDA_S), B as rows of BN (stride LDB_S).  ChunkA /
+// ChunkB stage 16-byte chunks produced by a functor f(k0, row, kc) (8 A
+// values: block row `row`, k = k0+kc..+7) or f(k0, kr, jc) (8 B values:
+// k = k0+kr, block columns jc..+7).
+template <class T, class F>
+struct ChunkA {
+    F f;
+    uint4 r[T::A_CPT];
+    __device__ __forceinline__ void load(int64_t k0)
+    {
+#pragma unroll
+        for (int q = 0; q < T::A_CPT; q++) {
+            const int c = threadIdx.x + q * T::NT;
+            if (T::A_CH % T::NT == 0 || c < T::A_CH) r[q] = f(k0, c / (T::BK / 8), (c % (T::BK / 8)) * 8);
+        }
+    }
+    template <bool H>
+    __device__ __forceinline__ void store(u16 *as) const
+    {
+#pragma unroll
+        for (int q = 0; q < T::A_CPT; q++) {
+            const int c = threadIdx.x + q * T::NT;
+            if (T::A_CH % T::NT == 0 || c < T::A_CH)
+                *(uint4 *)(as + (c / (T::BK / 8)) * T::LDA_S + (c % (T::BK / 8)) * 8) = image<H>(r[q]);
+        }
+    }
+};
+
+template <class T, class F>
+struct ChunkB {
+    F f;
+    uint4 r[T::B_CPT];
+    __device__ __forceinline__ void load(int64_t k0)
+    {
+#pragma unroll
+        for (int q = 0; q < T::B_CPT; q++) {
+            const int c = threadIdx.x + q * T::NT;
+            if (T::B_CH % T::NT == 0 || c < T::B_CH) r[q] = f(k0, c / (T::BN / 8), (c % (T::BN / 8)) * 8);
+        }
+    }
+    template <bool H>
+    __device__ __forceinline__ void store(u16 *bs) const
+    {
+#pragma unroll
+        for (int q = 0; q < T::B_CPT; q++) {
+            const int c = threadIdx.x + q * T::NT;
+            if (T::B_CH % T::NT == 0 || c < T::B_CH)
+                *(uint4 *)(bs + (c / (T::BN / 8)) * T::LDB_S + (c % (T::BN / 8)) * 8) = image<H>(r[q]);
+        }
+    }
+};
+
+template <class T, class F>
+__device__ __forceinline__ ChunkA<T, F> chunk_a(F f)
+{
+    return ChunkA<T, F>{f, {}};
+}
+template <class T, class F>
+__device__ __forceinline__ ChunkB<T, F> chunk_b(F f)
+{
+    return ChunkB<T, F>{f, {}};
+}
+
+// The k loop of one BM x BN block over nk BK-deep slices, in form H.
+template <class T, bool H, class AOp, class BOp>
+__device__ __forceinline__ void tile_kloop(int64_t nk, AOp &aop, BOp &bop, u16 *lds, TileAcc<T> &acc)
 {
     const int tid = threadIdx.x;
     const int tx = tid % T::TX, ty = tid / T::TX;
     // Stage s holds A at lds + s*STAGE and B at lds + s*STAGE + A_STAGE.
     constexpr int STAGE = T::A_STAGE + T::B_STAGE;
+    constexpr u16 INIT = H ? 0x7C00 : 0xFFFF;
 
 #pragma unroll
     for (int r = 0; r < T::TM; r++)
 #pragma unroll
-        for (int c = 0; c < T::NACC; c++) acc.v[r][c] = (u16x2){0xFFFF, 0xFFFF};
+        for (int c = 0; c < T::NACC; c++) acc.v[r][c] = (u16x2){INIT, INIT};
 
     if (nk == 0) return;
 
-    uint4 ra[T::A_CPT], rb[T::B_CPT];
-    auto gload = [&](int64_t kt) {
-        const int64_t k0 = kt * T::BK;
-#pragma unroll
-        for (int q = 0; q < T::A_CPT; q++) {
-            const int c = tid + q * T::NT;
-            if (T::A_CH % T::NT == 0 || c < T::A_CH) ra[q] = aload(k0, c / (T::BK / 8), (c % (T::BK / 8)) * 8);
-        }
-#pragma unroll
-        for (int q = 0; q < T::B_CPT; q++) {
-            const int c = tid + q * T::NT;
-            if (T::B_CH % T::NT == 0 || c < T::B_CH) rb[q] = bload(k0, c / (T::BN / 8), (c % (T::BN / 8)) * 8);
-        }
-    };
-    auto sstore = [&](int stage) {
-#pragma unroll
-        for (int q = 0; q < T::A_CPT; q++) {
-            const int c = tid + q * T::NT;
-            if (T::A_CH % T::NT == 0 || c < T::A_CH) {
-                const int row = c / (T::BK / 8), kc = (c % (T::BK / 8)) * 8;
-                *(uint4 *)(lds + stage * STAGE + row * T::LDA_S + kc) = ra[q];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < T::B_CPT; q++) {
-            const int c = tid + q * T::NT;
-            if (T::B_CH % T::NT == 0 || c < T::B_CH) {
-                const int kr = c / (T::BN / 8), jc = (c % (T::BN / 8)) * 8;
-                *(uint4 *)(lds + stage * STAGE + T::A_STAGE + kr * T::LDB_S + jc) = rb[q];
-            }
-        }
-    };
-    gload(0);
-    sstore(0);
+    aop.load(0);
+    bop.load(0);
+    aop.template store<H>(lds);
+    bop.template store<H>(lds + T::A_STAGE);
     __syncthreads();
 
     for (int64_t kt = 0; kt < nk; kt++) {
         const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) gload(kt + 1);  // next slice in flight during the math
+        if (kt + 1 < nk) {  // next slice in flight during the math
+            aop.load((kt + 1) * T::BK);
+            bop.load((kt + 1) * T::BK);
+        }
         const u16 *as = lds + cur * STAGE;
         const u16 *bs = as + T::A_STAGE;
 #pragma unroll 1
@@ -134,50 +189,149 @@ __device__ __forceinline__ void tile_mainloop_with(int64_t nk, ALoad aload, BLoa
             uint4 af[T::TM];
 #pragma unroll
             for (int r = 0; r < T::TM; r++) af[r] = *(const uint4 *)(as + (ty + r * T::TY) * T::LDA_S + kk);
-            // B fragments of row kk + kq; the next row's are read while this
-            // one is consumed.
-            uint4 bf[T::TN / 8], bn[T::TN / 8];
+            auto brow = [&](int k, int c8) {
+                return *(const uint4 *)(bs + k * T::LDB_S + c8 * (T::TX * 8) + tx * 8);
+            };
+            if constexpr (!H) {
+                // B fragments of row kk + kq; the next row's are read while
+                // this one is consumed.
+                uint4 bf[T::TN / 8], bn[T::TN / 8];
 #pragma unroll
-            for (int c8 = 0; c8 < T::TN / 8; c8++)
-                bf[c8] = *(const uint4 *)(bs + kk * T::LDB_S + c8 * (T::TX * 8) + tx * 8);
+                for (int c8 = 0; c8 < T::TN / 8; c8++) bf[c8] = brow(kk, c8);
 #pragma unroll
-            for (int kq = 0; kq < 8; kq++) {
-                if (kq < 7) {
+                for (int kq = 0; kq < 8; kq++) {
+                    if (kq < 7) {
 #pragma unroll
-                    for (int c8 = 0; c8 < T::TN / 8; c8++)
-                        bn[c8] = *(const uint4 *)(bs + (kk + kq + 1) * T::LDB_S + c8 * (T::TX * 8) + tx * 8);
+                        for (int c8 = 0; c8 < T::TN / 8; c8++) bn[c8] = brow(kk + kq + 1, c8);
+                    }
+#pragma unroll
+                    for (int r = 0; r < T::TM; r++) {
+                        const u16x2 ap = as_u16x2(comp(af[r], kq >> 1));
+                        const u16x2 a2 = (kq & 1) ? ap.yy : ap.xx;
+#pragma unroll
+                        for (int c8 = 0; c8 < T::TN / 8; c8++)
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                u16x2 &d = acc.v[r][c8 * 4 + q];
+                                d = min2(d, add_sat(a2, as_u16x2(comp(bf[c8], q))));
+                            }
+                    }
+#pragma unroll
+                    for (int c8 = 0; c8 < T::TN / 8; c8++) bf[c8] = bn[c8];
+                }
+            } else {
+                // Rows kk + kq and kk + kq + 1 together; the A register holds
+                // a_k in its low and a_(k+1) in its high half.
+                uint4 b0[T::TN / 8], b1[T::TN / 8], n0[T::TN / 8], n1[T::TN / 8];
+#pragma unroll
+                for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                    b0[c8] = brow(kk, c8);
+                    b1[c8] = brow(kk + 1, c8);
                 }
 #pragma unroll
-                for (int r = 0; r < T::TM; r++) {
-                    const u16x2 ap = as_u16x2(comp(af[r], kq >> 1));
-                    const u16x2 a2 = (kq & 1) ? ap.yy : ap.xx;
+                for (int kq = 0; kq < 8; kq += 2) {
+                    if (kq < 6) {
 #pragma unroll
-                    for (int c8 = 0; c8 < T::TN / 8; c8++)
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            u16x2 &d = acc.v[r][c8 * 4 + q];
-                            d = min2(d, add_sat(a2, as_u16x2(comp(bf[c8], q))));
+                        for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                            n0[c8] = brow(kk + kq + 2, c8);
+                            n1[c8] = brow(kk + kq + 3, c8);
                         }
-                }
+                    }
 #pragma unroll
-                for (int c8 = 0; c8 < T::TN / 8; c8++) bf[c8] = bn[c8];
+                    for (int r = 0; r < T::TM; r++) {
+                        const h16x2 ap = as_h16x2(comp(af[r], kq >> 1));
+                        const h16x2 alo = ap.xx, ahi = ap.yy;
+#pragma unroll
+                        for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                            // all eight sums first: a minimum3 that reads the
+                            // add just before it costs a wait state
+                            h16x2 s0[4], s1[4];
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                s0[q] = alo + as_h16x2(comp(b0[c8], q));
+                                s1[q] = ahi + as_h16x2(comp(b1[c8], q));
+                            }
+#pragma unroll
+                            for (int q = 0; q < 4; q++) {
+                                u16x2 &d = acc.v[r][c8 * 4 + q];
+                                const h16x2 m = __builtin_elementwise_minimum(
+                                    __builtin_elementwise_minimum(as_h16x2(as_u32(d)), s0[q]), s1[q]);
+                                d = as_u16x2(as_u32(m));
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                        b0[c8] = n0[c8];
+                        b1[c8] = n1[c8];
+                    }
+                }
             }
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
+        if (kt + 1 < nk) {
+            aop.template store<H>(lds + (cur ^ 1) * STAGE);
+            bop.template store<H>(lds + (cur ^ 1) * STAGE + T::A_STAGE);
+        }
         __syncthreads();
     }
 }
 
+// Converts the accumulators of an f16 pass back to uint16 (+inf -> 0xFFFF)
+// and returns true when one of them is not exact (finite, >= 0x800).
+template <class T>
+__device__ __forceinline__ bool tile_from_h16(TileAcc<T> &acc)
+{
+    bool redo = false;
+#pragma unroll
+    for (int r = 0; r < T::TM; r++)
+#pragma unroll
+        for (int c = 0; c < T::NACC; c++) {
+            u16x2 v = acc.v[r][c];
+            redo |= (v.x >= 0x800 && v.x != 0x7C00) || (v.y >= 0x800 && v.y != 0x7C00);
+            v.x = v.x == 0x7C00 ? (u16)0xFFFF : v.x;
+            v.y = v.y == 0x7C00 ? (u16)0xFFFF : v.y;
+            acc.v[r][c] = v;
+        }
+    return redo;
+}
+
+// The (min,+) block product: form H, with the uint16 recomputation for the
+// blocks whose f16 results are not all exact (block-uniform decision).
+template <class T, bool H, class AOp, class BOp>
+__device__ __forceinline__ void tile_product(int64_t nk, AOp &aop, BOp &bop, u16 *lds, TileAcc<T> &acc)
+{
+    if constexpr (H) {
+        tile_kloop<T, true>(nk, aop, bop, lds, acc);
+        if (!__syncthreads_or(tile_from_h16<T>(acc))) return;
+    }
+    tile_kloop<T, false>(nk, aop, bop, lds, acc);
+}
+
+// uint16 form only (kept for callers that stage operands themselves).
+template <class T, class AOp, class BOp>
+__device__ __forceinline__ void tile_mainloop_ops(int64_t nk, AOp &aop, BOp &bop, u16 *lds, TileAcc<T> &acc)
+{
+    tile_kloop<T, false>(nk, aop, bop, lds, acc);
+}
+
+// Functor form of the k loop (16-byte chunk producers for both operands).
+template <class T, bool H = false, class ALoad, class BLoad>
+__device__ __forceinline__ void tile_mainloop_with(int64_t nk, ALoad aload, BLoad bload, u16 *lds, TileAcc<T> &acc)
+{
+    auto aop = chunk_a<T>(aload);
+    auto bop = chunk_b<T>(bload);
+    tile_product<T, H>(nk, aop, bop, lds, acc);
+}
 
 // The plain product's k loop: A is M x K (lda), B is K x N (ldb), block at (m0, n0).
-template <class T>
+template <class T, bool H = false>
 __device__ __forceinline__ void tile_mainloop(const u16 *__restrict__ A, int64_t lda,
                                               const u16 *__restrict__ B, int64_t ldb,
                                               int64_t M, int64_t N, int64_t K, int64_t m0, int64_t n0,
                                               bool vec, u16 *lds, TileAcc<T> &acc)
 {
     const int64_t nk = (K + T::BK - 1) / T::BK;
-    tile_mainloop_with<T>(
+    tile_mainloop_with<T, H>(
         nk, [&](int64_t k0, int row, int kc) { return load8(A, lda, m0 + row, k0 + kc, M, K, vec); },
         [&](int64_t k0, int kr, int jc) { return load8(B, ldb, k0 + kr, n0 + jc, K, N, vec); }, lds, acc);
 }

@@ -89,6 +89,62 @@ def test_gemm_extremes(mpr):
     assert np.all(_host(C0) == 0xFFFF)
 
 
+def _all_cfg_equal(mpr, X, Y, what):
+    ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
+    A, B = _dev(mpr, X), _dev(mpr, Y)
+    for cfg in range(mpr.gemm_config_count()):
+        C = mpr.minplus_gemm(A, B, cfg=cfg)
+        assert np.array_equal(_host(C), ref), (what, cfg, mpr.gemm_config_info(cfg))
+    return ref
+
+
+def test_gemm_f16_form_boundaries(mpr):
+    """Cases aimed at the f16 form of the product configurations: sums on
+    both sides of 2048 (exact below, recomputed in uint16 from there), the
+    clamp of finite values >= 0x800, finite values 0x7C00..0x7FFF (f16
+    infinity / NaN patterns), and sums up to 0xFFFE that must stay finite."""
+    print("f16 boundaries", flush=True)
+    M, N, K = 200, 190, 5
+    rng = np.random.default_rng(11)
+    # around 2048: entries 1000..1050, sums 2000..2100, minima of few terms
+    X = rng.integers(1000, 1051, (M, K)).astype(np.uint16)
+    Y = rng.integers(1000, 1051, (K, N)).astype(np.uint16)
+    X[rng.random((M, K)) < 0.3] = 0xFFFF
+    ref = _all_cfg_equal(mpr, X, Y, "around 2048")
+    assert (ref < 2048).any() and ((ref >= 2048) & (ref != 0xFFFF)).any()
+    # exact 2047 / 2048 minima
+    X = np.full((70, 40), 0xFFFF, np.uint16)
+    Y = np.full((40, 66), 0xFFFF, np.uint16)
+    X[:, 3] = 1023
+    Y[3, :] = 1024          # 2047 everywhere ...
+    Y[3, ::2] = 1025        # ... or 2048 in even columns
+    ref = _all_cfg_equal(mpr, X, Y, "2047/2048")
+    assert (ref[:, 1::2] == 2047).all() and (ref[:, ::2] == 2048).all()
+    # f16 infinity / NaN bit patterns as finite values, sums up to 0xFFFE
+    X = rng.integers(0x7C00, 0x8000, (90, 70)).astype(np.uint16)
+    Y = rng.integers(0x7C00, 0x8000, (70, 80)).astype(np.uint16)
+    X[rng.random(X.shape) < 0.4] = 0xFFFF
+    Y[:, 5] = 0xFFFF
+    X[0, :] = 0x7FFF
+    Y[:, 0] = 0x7FFF
+    ref = _all_cfg_equal(mpr, X, Y, "0x7C00..0x7FFF")
+    assert ref[0, 0] == 0xFFFE and (ref[:, 5] == 0xFFFF).all()
+
+
+def test_gemm_f16_form_mixed_blocks(mpr):
+    """Small entries except for a band of rows of A and a band of columns of
+    B with large ones: only the blocks that meet the bands hold minima
+    >= 2048, so some blocks keep their f16 results and others recompute."""
+    print("f16 mixed blocks", flush=True)
+    M, N, K = 700, 650, 333
+    X = synth.random_matrix(M, K, 21, 0, 15, 0.3)
+    Y = synth.random_matrix(K, N, 22, 0, 15, 0.3)
+    X[300:340, :] = synth.random_matrix(40, K, 23, 3000, 9000, 0.2)
+    Y[:, 500:520] = synth.random_matrix(K, 20, 24, 0x7800, 0x7FFF, 0.2)
+    ref = _all_cfg_equal(mpr, X, Y, "mixed")
+    assert (ref[300:340] >= 2048).all() and (ref[:300, :500] < 64).all()
+
+
 def test_gemm_overflow_is_reported(mpr):
     X = synth.random_matrix(40, 40, 5, 0, 15, 0.3)
     X[3, 4] = 0x8000

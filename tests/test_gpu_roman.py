@@ -100,13 +100,33 @@ def test_sparse_period_matches(mpr):
         assert all(tr[k] == g["trace"][str(k)] for k in range(1, 301))
 
 
-def test_sparse_chain_random_and_edge_blocks(mpr):
+@pytest.mark.parametrize("arith", ["f16", "u16"])
+def test_sparse_chain_random_and_edge_blocks(mpr, arith):
+    """Both arithmetic forms of the compressed-K step; the last two cases
+    have entries large enough that the f16 form recomputes blocks."""
     import oracle as O
     import synth
 
-    for n, frac, e in [(700, 0.95, 6), (333, 0.99, 9), (129, 0.5, 5), (64, 0.9, 4)]:
-        X = synth.random_matrix(n, n, 77 + n, 0, 40, frac)
-        X[:, 64:128] = 0xFFFF  # an empty column block
-        N, R = mpr.minplus_power(mpr.to_device(X), e, mpr.CHAIN_SPARSE)
-        Nr, Rr = O.power_chain(O.from_u16(X), e)
-        assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), n
+    mpr.set_sparse_arith(arith)
+    try:
+        for n, frac, e, hi in [(700, 0.95, 6, 40), (333, 0.99, 9, 40), (129, 0.5, 5, 40), (64, 0.9, 4, 40),
+                               (300, 0.9, 4, 3000), (200, 0.97, 3, 0x7FFF)]:
+            X = synth.random_matrix(n, n, 77 + n, 0, hi, frac)
+            X[:, 64:128] = 0xFFFF  # an empty column block
+            N, R = mpr.minplus_power(mpr.to_device(X), e, mpr.CHAIN_SPARSE)
+            Nr, Rr = O.power_chain(O.from_u16(X), e)
+            assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), n
+    finally:
+        mpr.set_sparse_arith("f16")
+
+
+def test_sparse_chain_u16_digests(mpr):
+    mpr.set_sparse_arith("u16")
+    try:
+        g = load(7)
+        A = mpr.build_transfer(7)
+        for k in (2, 26, 300):
+            N, R = mpr.minplus_power(A, k, mpr.CHAIN_SPARSE)
+            assert digest(N, R) == g["digest_sha256"][str(k)], k
+    finally:
+        mpr.set_sparse_arith("f16")

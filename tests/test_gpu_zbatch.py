@@ -30,7 +30,7 @@ def _small_batch(mpr):
     return chains, mats
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", list(range(12)))
 def test_batch_matches_oracle_and_solo(mpr, cfg):
     print("batch cfg", cfg, flush=True)
     mpr.set_batch_config(cfg)
@@ -43,6 +43,27 @@ def test_batch_matches_oracle_and_solo(mpr, cfg):
             assert np.array_equal(R.cpu().numpy(), Rr)
             Ns, Rs = mpr.minplus_power(A, e, mpr.CHAIN)
             assert np.array_equal(Ns.cpu().numpy(), N.cpu().numpy()) and torch.equal(Rs, R)
+    finally:
+        mpr.set_batch_config(-1)
+
+
+@pytest.mark.parametrize("cfg", [0, 6, 11])
+def test_batch_large_entries(mpr, cfg):
+    """Entries 2100..3000 (every finite product entry >= 2100, so the f16
+    form recomputes every block in uint16) beside a small-entry chain."""
+    print("batch large", cfg, flush=True)
+    mpr.set_batch_config(cfg)
+    try:
+        mats, chains = [], []
+        for i, (n, e) in enumerate([(150, 4), (300, 3), (77, 6)]):
+            X = synth.random_matrix(n, n, 900 + i, 0 if i == 0 else 2100, 31 if i == 0 else 3000, 0.2)
+            mats.append((X, e))
+            chains.append((mpr.to_device(X), e, mpr.alloc_matrix(n, n), torch.empty(n, dtype=torch.int64,
+                                                                                    device="cuda")))
+        mpr.batch_power(chains)
+        for (A, e, N, R), (X, _) in zip(chains, mats):
+            Nr, Rr = O.power_chain(O.from_u16(X), e)
+            assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
     finally:
         mpr.set_batch_config(-1)
 
