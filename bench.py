@@ -268,7 +268,8 @@ def bench_config2(args, mpr, torch):
     mpr.check_status(st)
     pairs = float(n) ** 3
     return {"metric": "min-plus GOPS, N=8192 single product and 64-power chain", "value": round(63 * pairs / t_chain / 1e9, 1),
-            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16",
+            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": mpr.gemm_config_info(mpr.gemm_pick_config(n, n, n))["arith"],
             "data": "synthetic (SplitMix64 seed 3; uniform [0,15], 30% infinity)",
             "config": {"workload": "A^64 by the chain, N=8192, normalised every step", "n": n, "e": e},
             "single_product_ms": round(t_single * 1e3, 3), "single_product_gpairs": round(pairs / t_single / 1e9, 1),
@@ -333,7 +334,9 @@ def bench_config3(args, mpr, torch):
     if args.with_m9:
         per_m[9] = bench_m9(mpr, torch)
     return {"metric": "Roman transfer powers to n=300 (m=6,7,8): chain GOPS", "value": round(tot / tt / 1e9, 1),
-            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u16", "data": "transfer matrices",
+            "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": mpr.gemm_config_info(mpr.gemm_pick_config(7411, 7411, 7411))["arith"],
+            "data": "transfer matrices",
             "config": {"workload": "A(G)^300 by chain and by squaring, period search, gamma_R(3..300)"},
             "per_m": per_m}
 
@@ -389,7 +392,8 @@ def bench_m10(args, mpr, torch):
     print("m10: %d powers in %.1f s, period %s" % (kmax, t, (mu, lam, c)), file=sys.stderr, flush=True)
     gam = {k: int(tr[k]) for k in range(3, kmax + 1)}
     out = {"metric": "gamma_R(P_10 x C_n): seconds for the m=10 period search (A^1..A^kmax, N=64769)",
-           "value": round(t, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "u16",
+           "value": round(t, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f16" if args.m10_sparse else mpr.gemm_config_info(mpr.gemm_pick_config(n, n, n))["arith"],
            "data": "transfer matrix m=10",
            "dense_equivalent_gpairs": round((kmax - 1) * float(n) ** 3 / t / 1e9, 1),
            "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n,
