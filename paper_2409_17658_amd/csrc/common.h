@@ -70,7 +70,6 @@ __device__ __forceinline__ uint32_t to_h16(uint32_t x)
     const i16x2 c = __builtin_elementwise_min(__builtin_bit_cast(i16x2, x), (i16x2){0x800, 0x800});
     return as_u32(min2(__builtin_bit_cast(u16x2, c), (u16x2){0x7C00, 0x7C00}));
 }
-__device__ __forceinline__ u16 to_h16_1(u16 x) { return x == 0xFFFF ? (u16)0x7C00 : (x < 0x800 ? x : (u16)0x800); }
 
 __device__ __forceinline__ uint32_t comp(const uint4 &v, int q)
 {

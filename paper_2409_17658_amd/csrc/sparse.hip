@@ -120,6 +120,14 @@ __global__ __launch_bounds__(256) void sp_fill_kernel(const u16 *A, int64_t lda,
     }
 }
 
+// One value's f16 image (to_h16 for a single uint16): signed, 0xFFFF is -1
+// and survives min(., 0x800); unsigned, it then meets 0x7C00.
+__device__ __forceinline__ u16 to_h16_1(u16 x)
+{
+    const short c = __builtin_elementwise_min((short)x, (short)0x800);
+    return __builtin_elementwise_min((u16)c, (u16)0x7C00);
+}
+
 // Left operand of the compressed-K step: N[m0 + row][L_J[k]] for the BK-deep
 // slice.  Thread t handles k = t % BK (fixed: NT is a multiple of BK), so it
 // reads its index once per slice, and rows t / BK + e * (NT / BK); a wave thus
@@ -133,11 +141,17 @@ struct GatherA {
     const gu16 *N;
     int64_t ldn, n, m0;
     const __attribute__((address_space(1))) int32_t *idx;
+    bool full;  // all BM rows of the block are < n (block-uniform)
     uint32_t v[PER];
     __device__ __forceinline__ void load(int64_t k0)
     {
         const int k = (int)(threadIdx.x % T::BK), r0 = (int)(threadIdx.x / T::BK);
         const int64_t col = idx[k0 + k];
+        if (full) {
+#pragma unroll
+            for (int e = 0; e < PER; e++) v[e] = N[(m0 + r0 + e * RSTEP) * ldn + col];
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < PER; e++) {
             const int64_t r = m0 + r0 + e * RSTEP;
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) v
     const __attribute__((address_space(1))) int32_t *gi = glob(idx) + kbeg;
     const gu16 *gB = glob(Bp) + kbeg * SBN;
     TileAcc<SCfg> acc;
-    GatherA<SCfg> aop{gN, ldn, n, m0, gi, {}};
+    GatherA<SCfg> aop{gN, ldn, n, m0, gi, m0 + SCfg::BM <= n, {}};
     auto bop = chunk_b<SCfg>([&](int64_t k0, int kr, int jc) { return gload16(gB + (k0 + kr) * SBN + jc); });
     tile_product<SCfg, H>(K / SBK, aop, bop, lds, acc);
     tile_store<SCfg>(C, ldc, n, n, m0, n0, vec != 0, acc);
