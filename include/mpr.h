@@ -279,6 +279,12 @@ mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count,
  * can be captured into a HIP graph).  Results land in each N_out / R_out. */
 mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream stream);
 
+/* Describes the plan held in ws: configuration, workgroups of the
+ * persistent grid (resident workgroups per CU x CUs, at most the number of
+ * panels) and number of panels (host ints, any may be NULL).  MPR_EINVAL if
+ * ws holds no plan. */
+mpr_status mpr_batch_plan_info(void *ws, int *cfg, int *grid, int *panels);
+
 /* Plan + launch. */
 mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count,
                            void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);

@@ -103,6 +103,7 @@ _SIGS = {
     "mpr_batch_config_count": (_I, []),
     "mpr_batch_config_info": (_I, [_I, _P, _P, _P]),
     "mpr_set_sparse_arith": (_I, [_I]),
+    "mpr_batch_plan_info": (_I, [_P, _P, _P, _P]),
     "mpr_set_batch_config": (_I, [_I]),
     "mpr_batch_graph_create": (_I, [_P, _P, _P, _P]),
     "mpr_graph_launch": (_I, [_P, _P]),
@@ -447,6 +448,13 @@ def batch_config_info(cfg: int):
 def set_sparse_arith(arith: str):
     """'f16' (default) or 'u16' for the compressed-K chain steps."""
     _ok(lib().mpr_set_sparse_arith(ARITH_F16 if arith == "f16" else ARITH_U16), "mpr_set_sparse_arith")
+
+
+def batch_plan_info(ws):
+    """(configuration, persistent-grid workgroups, panels) of the plan in ws."""
+    v = [ctypes.c_int() for _ in range(3)]
+    _ok(lib().mpr_batch_plan_info(_ptr(ws), *[ctypes.byref(x) for x in v]), "mpr_batch_plan_info")
+    return tuple(x.value for x in v)
 
 
 def set_batch_config(cfg: int):

@@ -471,6 +471,17 @@ extern "C" mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream s
     return check_launch();
 }
 
+extern "C" mpr_status mpr_batch_plan_info(void *ws, int *cfg, int *grid, int *panels)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(ws);
+    if (it == g_plans.end()) return MPR_EINVAL;
+    if (cfg) *cfg = it->second.cfg;
+    if (grid) *grid = it->second.grid;
+    if (panels) *panels = it->second.n_items;
+    return MPR_OK;
+}
+
 extern "C" mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count, void *ws, size_t ws_bytes,
                                       int32_t *d_status, mpr_stream stream)
 {
