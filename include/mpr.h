@@ -128,7 +128,10 @@ mpr_status mpr_build_border_transfer(int m, uint16_t *A, int64_t lda, int64_t *s
  * caller guarantees the bound).  Finite outputs are exact values in
  * [0, 0xFFFE].  M, N, K >= 0 (an empty K gives an all-MPR_INF C).  C must
  * not overlap A or B.  Fast path: A, B, C 16-byte aligned and lda, ldb, ldc
- * multiples of 8; any other layout takes a slower element-wise path. */
+ * multiples of 8; any other layout takes a slower element-wise path.  The
+ * configuration the tile table picks may compute in the f16 form
+ * (MPR_ARITH_F16): the result is the same, but tiles whose minima reach
+ * 2048 are computed twice (about 1.75x the uint16 time for such tiles). */
 mpr_status mpr_minplus_gemm(int64_t M, int64_t N, int64_t K,
                             const uint16_t *A, int64_t lda,
                             const uint16_t *B, int64_t ldb,

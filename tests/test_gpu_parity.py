@@ -221,6 +221,21 @@ def test_build_transfer_m9_sampled_rows(mpr):
     assert np.array_equal(_host(A)[rows], _u16(O.transfer_rows(9, rows)))
 
 
+@pytest.mark.parametrize("m", [10, 11])
+def test_build_transfer_largest_sampled_rows(mpr, m):
+    """The largest builds the API accepts (C_10 = 64769, C_11 = 191476
+    states: a 73 GB matrix at m = 11): sampled rows, including the first and
+    the last, against the oracle's row-restricted builder."""
+    print("transfer m", m, flush=True)
+    n = mpr.transfer_size(m)
+    A = mpr.build_transfer(m)
+    rows = [0, 1, n // 3, n // 2 + 7, n - 2, n - 1]
+    got = A[rows].cpu().numpy()
+    del A
+    torch.cuda.empty_cache()
+    assert np.array_equal(got, _u16(O.transfer_rows(m, rows)))
+
+
 # ------------------------------------------------------------------ powers
 @pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("m,e", [(3, 1), (3, 2), (3, 17), (4, 23), (5, 12), (6, 9)])
