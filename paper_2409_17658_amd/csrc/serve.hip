@@ -164,6 +164,14 @@ struct Server {
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
 
+// The worker's writes to the counters that mpr_server_stats_get reads.
+template <class F>
+static void stats_update(Server &S, F f)
+{
+    std::lock_guard<std::mutex> lk(S.mu);
+    f(S.stats);
+}
+
 static size_t ladder_bytes(int m, int B, int G, int64_t *n_out, int64_t *ld_out)
 {
     const int64_t n = transfer_size(m), ld = round_up(n, 8);
@@ -239,7 +247,7 @@ static mpr_status start_build(Server &S, Ladder &L)
     L.state = Ladder::BUILDING;
     L.build_s0 = S.now();
     S.resident += L.bytes;
-    S.stats.builds++;
+    stats_update(S, [](mpr_server_stats &t) { t.builds++; });
     return MPR_OK;
 }
 
@@ -284,15 +292,20 @@ static bool admit(Server &S, int m)
         }
         if (!victim) return false;
         free_ladder(S, *victim);
-        S.stats.evictions++;
+        stats_update(S, [](mpr_server_stats &t) { t.evictions++; });
     }
     Ladder &L = S.ladders[m];
     L.m = m;
     const mpr_status e = start_build(S, L);
     if (e != MPR_OK) {
         if (L.mem) {
+            (void)hipStreamSynchronize(S.bstream);  // part of the build may be enqueued
             (void)hipFree(L.mem);
             L.mem = nullptr;
+        }
+        if (L.ready) {
+            (void)hipEventDestroy(L.ready);
+            L.ready = nullptr;
         }
         L.state = Ladder::FAILED;
         L.fail_status = e;
@@ -340,10 +353,16 @@ static void worker_main(Server *Sp)
             if (hipMemcpy(&st, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) != hipSuccess)
                 st = MPR_EHIP;
-            L.state = st == 0 ? Ladder::READY : Ladder::FAILED;
-            if (st != 0) L.fail_status = st;
             L.build_s = S.now() - L.build_s0;
             L.last_use = S.now();
+            if (st == 0) {
+                L.state = Ladder::READY;
+            } else {  // the build is done with its memory: release it, keep the verdict
+                free_ladder(S, L);
+                L.m = kv.first;
+                L.state = Ladder::FAILED;
+                L.fail_status = st;
+            }
         }
         // 3. route new requests
         for (auto &r : fresh) {
@@ -361,7 +380,7 @@ static void worker_main(Server *Sp)
                 bool queued = std::find(S.admission.begin(), S.admission.end(), r.m) != S.admission.end();
                 if (!queued && !admit(S, r.m)) {
                     S.admission.push_back(r.m);
-                    S.stats.admission_waits++;
+                    stats_update(S, [](mpr_server_stats &t) { t.admission_waits++; });
                 }
             } else if (it->second.state == Ladder::BUILDING) {
                 r.cold = true;
@@ -440,10 +459,12 @@ static void worker_main(Server *Sp)
             slot->reqs = batch;
             slot->busy = true;
             slot->t_launch = S.now();
-            S.stats.batches++;
-            S.stats.max_batch_seen = std::max<int64_t>(S.stats.max_batch_seen, nq);
+            stats_update(S, [nq](mpr_server_stats &t) {
+                t.batches++;
+                t.max_batch_seen = std::max<int64_t>(t.max_batch_seen, nq);
+            });
         }
-        S.stats.resident_bytes = (int64_t)S.resident;
+        stats_update(S, [&S](mpr_server_stats &t) { t.resident_bytes = (int64_t)S.resident; });
     }
 }
 
