@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "trace_tile.h"
 
 namespace mpr {
 
@@ -320,49 +321,38 @@ mpr_status fill_i32_launch(int32_t *p, int64_t count, int32_t v, hipStream_t s)
 }
 
 // Trace of (RX (+) X) (x) (RY (+) Y): min over (i, l) of
-// RX[i] + X[i][l] + RY[l] + Y[l][i].  A 64 x 64 block of (i, l) pairs reads
-// X[i0.., l0..] and Y[l0.., i0..] as row segments; Y's block is transposed
-// through LDS so both operands are read with unit stride.
-constexpr int TP = 64;
+// RX[i] + X[i][l] + RY[l] + Y[l][i], one tile per block (trace_tile.h).
 __global__ __launch_bounds__(256) void trace_product_kernel(const u16 *X, const int64_t *RX, const u16 *Y,
-                                                            const int64_t *RY, int64_t n, int64_t ld, int64_t *out)
+                                                            const int64_t *RY, int64_t n, int64_t ld, int64_t *out,
+                                                            int vec)
 {
-    __shared__ u16 yt[TP][TP + 2];
-    __shared__ int64_t sh[4];
-    const int64_t tiles = (n + TP - 1) / TP;
-    const int64_t bi = blockIdx.x / tiles, bl = blockIdx.x % tiles;
-    const int64_t i0 = bi * TP, l0 = bl * TP;
-    for (int t = threadIdx.x; t < TP * TP; t += 256) {
-        const int r = t / TP, c = t % TP;  // row l0 + r of Y, column i0 + c
-        const int64_t l = l0 + r, i = i0 + c;
-        yt[c][r] = (l < n && i < n) ? Y[l * ld + i] : (u16)0xFFFF;
-    }
-    __syncthreads();
+    // Grid-stride over the tiles with a running minimum and ONE atomic per
+    // block at the end: an atomic per tile on the one result word would
+    // serialise (over 100k of them at N = 21909).
+    __shared__ TPShared sh;
+    const int64_t tiles = (n + TPI - 1) / TPI, total = tiles * tiles;
     int64_t best = ROW_NONE;
-    for (int t = threadIdx.x; t < TP * TP; t += 256) {
-        const int r = t / TP, c = t % TP;  // pair (i0 + r, l0 + c)
-        const int64_t i = i0 + r, l = l0 + c;
-        if (i >= n || l >= n) continue;
-        const uint32_t x = X[i * ld + l], y = yt[r][c];
-        if (x == 0xFFFFu || y == 0xFFFFu) continue;
-        const int64_t rx = RX ? RX[i] : 0, ry = RY ? RY[l] : 0;
-        if (rx == ROW_NONE || ry == ROW_NONE) continue;
-        const int64_t v = rx + ry + (int64_t)(x + y);
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int64_t ti, tl;
+        tp_tile_of(t, tiles, ti, tl);
+        const int64_t v = tp_tile(X, RX, Y, RY, n, ld, ti * TPI, tl * TPL, vec != 0, sh);
         best = v < best ? v : best;
+        __syncthreads();  // the next tile reuses sh
     }
-    best = block_min_i64(best, sh);
     if (threadIdx.x == 0 && best != ROW_NONE) atomicMin((long long *)out, (long long)best);
 }
 
 mpr_status trace_product_launch(const u16 *X, const int64_t *RX, const u16 *Y, const int64_t *RY, int64_t n,
                                 int64_t ld, int64_t *out, hipStream_t s)
 {
+    static_assert(TPI == TPL, "square tiles");
     hipLaunchKernelGGL(fill_i64_kernel, dim3(1), dim3(64), 0, s, out, (int64_t)1, ROW_NONE);
     mpr_status e = check_launch();
     if (e != MPR_OK || n == 0) return e;
-    const int64_t tiles = (n + TP - 1) / TP;
-    if (tiles * tiles > INT32_MAX) return MPR_EUNSUPPORTED;
-    hipLaunchKernelGGL(trace_product_kernel, dim3((unsigned)(tiles * tiles)), dim3(256), 0, s, X, RX, Y, RY, n, ld, out);
+    const int64_t tiles = (n + TPI - 1) / TPI;
+    const int vec = aligned16(X) && aligned16(Y) && ld % 8 == 0;
+    const int64_t grid = std::min<int64_t>(tiles * tiles, (int64_t)device_cu_count() * TP_BLOCKS_PER_CU);
+    hipLaunchKernelGGL(trace_product_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, RX, Y, RY, n, ld, out, vec);
     return check_launch();
 }
 

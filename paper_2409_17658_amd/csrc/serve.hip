@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "common.h"
+#include "trace_tile.h"
 
 namespace mpr {
 
@@ -41,19 +42,23 @@ struct TPDesc {
     const u16 *Y;
     const int64_t *RY;
     int64_t n, ld, tiles, first_block;
+    int vec;
 };
 
-constexpr int GT = 64;
+constexpr int GT = TPI;  // square tiles of the trace routine
 
+// Grid-stride over the tiles of all queries of the batch (query q owns tiles
+// [first_block, first_block + tiles^2)); a block keeps a running minimum for
+// the query it is in and issues one atomic each time it leaves a query.
 __global__ __launch_bounds__(256) void grouped_trace_product_kernel(const TPDesc *__restrict__ d, int nq,
-                                                                    int64_t *out)
+                                                                    int64_t total, int64_t *out)
 {
-    __shared__ u16 yt[GT][GT + 2];
-    __shared__ int64_t sh[4];
-    __shared__ int qsel;
-    const int64_t b = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int lo = 0, hi = nq - 1;  // last q with first_block <= b
+    static_assert(TPI == TPL, "square tiles");
+    __shared__ TPShared sh;
+    int cur = -1;
+    int64_t best = ROW_NONE;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        int lo = 0, hi = nq - 1;  // last q with first_block <= b (every thread, same answer)
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
             if (d[mid].first_block <= b)
@@ -61,38 +66,19 @@ __global__ __launch_bounds__(256) void grouped_trace_product_kernel(const TPDesc
             else
                 hi = mid - 1;
         }
-        qsel = lo;
-    }
-    __syncthreads();
-    const TPDesc q = d[qsel];
-    const int64_t t = b - q.first_block;
-    const int64_t i0 = (t / q.tiles) * GT, l0 = (t % q.tiles) * GT;
-    for (int e = threadIdx.x; e < GT * GT; e += 256) {
-        const int r = e / GT, c = e % GT;
-        const int64_t l = l0 + r, i = i0 + c;
-        yt[c][r] = (l < q.n && i < q.n) ? q.Y[l * q.ld + i] : (u16)0xFFFF;
-    }
-    __syncthreads();
-    int64_t best = ROW_NONE;
-    for (int e = threadIdx.x; e < GT * GT; e += 256) {
-        const int r = e / GT, c = e % GT;
-        const int64_t i = i0 + r, l = l0 + c;
-        if (i >= q.n || l >= q.n) continue;
-        const uint32_t x = q.X[i * q.ld + l], y = yt[r][c];
-        if (x == 0xFFFFu || y == 0xFFFFu) continue;
-        const int64_t rx = q.RX[i], ry = q.RY[l];
-        if (rx == ROW_NONE || ry == ROW_NONE) continue;
-        const int64_t v = rx + ry + (int64_t)(x + y);
+        if (lo != cur) {
+            if (threadIdx.x == 0 && cur >= 0 && best != ROW_NONE) atomicMin((long long *)&out[cur], (long long)best);
+            cur = lo;
+            best = ROW_NONE;
+        }
+        const TPDesc q = d[lo];
+        int64_t ti, tl;
+        tp_tile_of(b - q.first_block, q.tiles, ti, tl);
+        const int64_t v = tp_tile(q.X, q.RX, q.Y, q.RY, q.n, q.ld, ti * GT, tl * GT, q.vec != 0, sh);
         best = v < best ? v : best;
+        __syncthreads();  // the next tile reuses sh
     }
-    best = wave_min_i64(best);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t v = sh[0];
-        for (int w = 1; w < 4; w++) v = sh[w] < v ? sh[w] : v;
-        if (v != ROW_NONE) atomicMin((long long *)&out[qsel], (long long)v);
-    }
+    if (threadIdx.x == 0 && cur >= 0 && best != ROW_NONE) atomicMin((long long *)&out[cur], (long long)best);
 }
 
 __global__ void fill_none_kernel(int64_t *p, int count)
@@ -433,7 +419,8 @@ static void worker_main(Server *Sp)
                 Ladder &L = S.ladders[r.m];
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
                 const int64_t tiles = (L.n + GT - 1) / GT;
-                slot->desc_host[q] = TPDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, tiles, blocks};
+                const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
+                slot->desc_host[q] = TPDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, tiles, blocks, vec};
                 blocks += tiles * tiles;
                 L.inflight++;
                 L.last_use = S.now();
@@ -443,8 +430,9 @@ static void worker_main(Server *Sp)
             bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TPDesc) * nq, hipMemcpyHostToDevice,
                                      s) == hipSuccess;
             hipLaunchKernelGGL(fill_none_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, slot->out_dev, nq);
-            hipLaunchKernelGGL(grouped_trace_product_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
-                               nq, slot->out_dev);
+            const int64_t grid = std::min<int64_t>(blocks, (int64_t)device_cu_count() * TP_BLOCKS_PER_CU);
+            hipLaunchKernelGGL(grouped_trace_product_kernel, dim3((unsigned)grid), dim3(256), 0, s, slot->desc_dev,
+                               nq, blocks, slot->out_dev);
             ok = ok && hipGetLastError() == hipSuccess;
             ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * nq, hipMemcpyDeviceToHost, s) == hipSuccess;
             ok = ok && hipEventRecord(slot->done, s) == hipSuccess;

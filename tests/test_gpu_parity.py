@@ -299,6 +299,48 @@ def test_traces(mpr):
     assert got == ref
 
 
+def _trace_ref(X, rx, Y, ry):
+    return O.trace(*O.product_of_powers(O.from_u16(X), rx, O.from_u16(Y), ry))
+
+
+def test_trace_of_product_offsets_and_layouts(mpr):
+    """Tiles whose offsets spread past 2^28 (int64 path) beside tiles that
+    do not (32-bit path), huge offsets with a small spread, empty rows and
+    whole empty tiles, NULL offsets, and a row stride that is not a
+    multiple of 8 (element-wise loads)."""
+    n = 300
+    X = synth.random_matrix(n, n, 31, 0, 40, 0.3)
+    Y = synth.random_matrix(n, n, 32, 0, 40, 0.3)
+    base = np.arange(n, dtype=np.int64) % 9
+    cases = []
+    wide = base.copy()
+    wide[:64] += (np.arange(64, dtype=np.int64) * 37 % 5) << 40  # only the first row tile is wide ...
+    wide[64:] += 1000  # ... and it holds the minimum
+    cases.append(("wide rows", wide, base))
+    cases.append(("wide inner", base, wide))
+    cases.append(("huge base", base + (1 << 50), base + 123456789012))
+    emp = base.copy()
+    emp[64:128] = O.INF  # a whole empty row tile
+    emp[7] = O.INF
+    cases.append(("empty rows", emp, base))
+    for name, rx, ry in cases:
+        print("trace", name, flush=True)
+        got = int(mpr.trace_of_product(_dev(mpr, X), torch.from_numpy(rx).cuda(), _dev(mpr, Y),
+                                       torch.from_numpy(ry).cuda()).item())
+        assert got == _trace_ref(X, rx, Y, ry), name
+    zero = np.zeros(n, dtype=np.int64)
+    got = int(mpr.trace_of_product(_dev(mpr, X), None, _dev(mpr, Y), None).item())
+    assert got == _trace_ref(X, zero, Y, zero)
+    # row stride n + 3 for both operands
+    Xp = np.full((n, n + 3), 0xFFFF, np.uint16)
+    Yp = np.full((n, n + 3), 0xFFFF, np.uint16)
+    Xp[:, :n], Yp[:, :n] = X, Y
+    Xd, Yd = torch.from_numpy(Xp).cuda()[:, :n], torch.from_numpy(Yp).cuda()[:, :n]
+    assert Xd.stride(0) % 8
+    got = int(mpr.trace_of_product(Xd, torch.from_numpy(base).cuda(), Yd, torch.from_numpy(base).cuda()).item())
+    assert got == _trace_ref(X, base, Y, base)
+
+
 # ------------------------------------------------------------------ gamma_R and periods
 def test_config1_gamma_m3(mpr):
     """P_3 x C_n for n = 3..40 from one GPU chain, vs oracle and brute force."""
