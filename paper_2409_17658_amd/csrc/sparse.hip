@@ -80,6 +80,23 @@ __global__ __launch_bounds__(1024) void sp_scan_kernel(const int64_t *counts, in
     }
 }
 
+// order[r] = the column block with the r-th largest |L_J| (ties by index):
+// the step launches the costliest blocks first so the launch does not end
+// on a few long blocks (|L_J| varies by 50x within one transfer matrix).
+// One block.
+__global__ __launch_bounds__(1024) void sp_order_kernel(const int64_t *counts, int64_t nblk, int32_t *order)
+{
+    for (int64_t J = threadIdx.x; J < nblk; J += 1024) {
+        const int64_t c = counts[J];
+        int64_t rank = 0;
+        for (int64_t K = 0; K < nblk; K++) {
+            const int64_t d = counts[K];
+            rank += (d > c) || (d == c && K < J);
+        }
+        order[rank] = (int32_t)J;
+    }
+}
+
 // Ordered compaction of block J: idx[off[J] + t] = t-th row of L_J and
 // Bp[(off[J] + t) * SBN + c] = A[l][j0 + c]; padding rows are row 0 / infinite.
 __global__ __launch_bounds__(256) void sp_fill_kernel(const u16 *A, int64_t lda, int64_t n, const int64_t *off,
@@ -172,18 +189,18 @@ struct GatherA {
 template <bool H>
 __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) void sp_step_kernel(const u16 *__restrict__ Np, int64_t ldn, int64_t n,
                                                            const int64_t *__restrict__ off,
+                                                           const int32_t *__restrict__ order,
                                                            const int32_t *__restrict__ idx,
                                                            const u16 *__restrict__ Bp, u16 *__restrict__ C,
                                                            int64_t ldc, int tiles_m, int nblk, int vec)
 {
     __shared__ __attribute__((aligned(16))) u16 lds[SCfg::LDS_ELEMS];
-    // same XCD-aware order as the plain product
-    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
-    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    // Column blocks costliest first (order[]), all row tiles of one column
+    // block consecutively; consecutive blocks go to different XCDs, so every
+    // XCD gets the same mix of costs.
+    const int t = (int)blockIdx.x;
     if (t >= tiles_m * nblk) return;
-    constexpr int G = 8;
-    const int width = G * nblk, first = (t / width) * G, gs = min(tiles_m - first, G), w = t % width;
-    const int tm = first + w % gs, J = w / gs;
+    const int tm = t % tiles_m, J = order[t / tiles_m];
     const int64_t m0 = (int64_t)tm * SCfg::BM, n0 = (int64_t)J * SBN;
     const int64_t kbeg = off[J], K = off[J + 1] - kbeg;
     const gu16 *gN = glob(Np);
@@ -201,14 +218,14 @@ size_t sparse_plan_bytes(int64_t n)
 {
     const int64_t nblk = (n + SBN - 1) / SBN;
     const int64_t rows = nblk * round_up(n, SBK);  // bound on sum of padded |L_J|
-    return (size_t)round_up((nblk + 1) * 8, 256) * 2 + (size_t)round_up(rows * 4, 256) +
-           (size_t)round_up(rows * SBN * 2, 256) + 256;
+    return (size_t)round_up((nblk + 1) * 8, 256) * 2 + (size_t)round_up(nblk * 4, 256) +
+           (size_t)round_up(rows * 4, 256) + (size_t)round_up(rows * SBN * 2, 256) + 256;
 }
 
 struct SparsePlan {
     int64_t nblk;
     int64_t *counts, *off;
-    int32_t *idx;
+    int32_t *order, *idx;
     u16 *Bp;
 };
 
@@ -222,6 +239,8 @@ static SparsePlan carve_plan(void *ws, int64_t n)
     c += round_up((p.nblk + 1) * 8, 256);
     p.off = (int64_t *)c;
     c += round_up((p.nblk + 1) * 8, 256);
+    p.order = (int32_t *)c;
+    c += round_up(p.nblk * 4, 256);
     p.idx = (int32_t *)c;
     c += round_up(rows * 4, 256);
     p.Bp = (u16 *)c;
@@ -234,6 +253,7 @@ mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hi
     const int vec = aligned16(A) && lda % 8 == 0;
     hipLaunchKernelGGL(sp_count_kernel, dim3((unsigned)p.nblk), dim3(256), 0, s, A, lda, n, p.counts, vec);
     hipLaunchKernelGGL(sp_scan_kernel, dim3(1), dim3(1024), 0, s, (const int64_t *)p.counts, p.nblk, p.off);
+    hipLaunchKernelGGL(sp_order_kernel, dim3(1), dim3(1024), 0, s, (const int64_t *)p.counts, p.nblk, p.order);
     hipLaunchKernelGGL(sp_fill_kernel, dim3((unsigned)p.nblk), dim3(256), 0, s, A, lda, n, (const int64_t *)p.off,
                        p.idx, p.Bp, vec);
     return check_launch();
@@ -249,8 +269,8 @@ mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u
     if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
     const int vec = aligned16(C) && ldc % 8 == 0;
     auto kernel = g_sparse_arith == MPR_ARITH_F16 ? sp_step_kernel<true> : sp_step_kernel<false>;
-    hipLaunchKernelGGL(kernel, dim3((unsigned)round_up(tiles, 8)), dim3(SCfg::NT), 0, s, Np, ldn, n,
-                       (const int64_t *)p.off, (const int32_t *)p.idx, (const u16 *)p.Bp, C, ldc, (int)tiles_m,
+    hipLaunchKernelGGL(kernel, dim3((unsigned)tiles), dim3(SCfg::NT), 0, s, Np, ldn, n, (const int64_t *)p.off,
+                       (const int32_t *)p.order, (const int32_t *)p.idx, (const u16 *)p.Bp, C, ldc, (int)tiles_m,
                        (int)p.nblk, vec);
     return check_launch();
 }
