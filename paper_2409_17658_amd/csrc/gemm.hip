@@ -16,6 +16,7 @@ using Cfg2 = TileCfg<256, 128, 32, 16, 8>;   // 256 threads, 16x8 per lane
 using Cfg3 = TileCfg<64, 64, 32, 4, 8>;      // 128 threads, small problems
 using Cfg4 = TileCfg<64, 256, 32, 8, 16>;    // 128 threads, 8x16 per lane
 using Cfg5 = TileCfg<128, 128, 16, 8, 8>;    // shallow k slices
+using Cfg6 = TileCfg<256, 128, 32, 8, 8>;    // 512 threads, 8x8 per lane
 
 // Blocks are handed to the 8 XCDs round-robin (block b runs on XCD b % 8).
 // Renumber so that each XCD receives a contiguous run of tiles, and walk the
@@ -89,12 +90,14 @@ struct CfgInfo {
 
 // Configurations 0..5 compute in uint16 (MPR_ARITH_U16); 6..11 are the
 // same tiles in the f16 form with the uint16 recomputation of inexact blocks
-// (MPR_ARITH_F16), which gives the same product bit for bit.
+// (MPR_ARITH_F16), which gives the same product bit for bit.  12 is a
+// 512-thread tile in uint16, 13 the same in the f16 form.
 #define MPR_CFG(T, H) {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, H ? MPR_ARITH_F16 : MPR_ARITH_U16, launch_cfg<T, H>}
 static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0, false), MPR_CFG(Cfg1, false), MPR_CFG(Cfg2, false),
                                 MPR_CFG(Cfg3, false), MPR_CFG(Cfg4, false), MPR_CFG(Cfg5, false),
                                 MPR_CFG(Cfg0, true),  MPR_CFG(Cfg1, true),  MPR_CFG(Cfg2, true),
-                                MPR_CFG(Cfg3, true),  MPR_CFG(Cfg4, true),  MPR_CFG(Cfg5, true)};
+                                MPR_CFG(Cfg3, true),  MPR_CFG(Cfg4, true),  MPR_CFG(Cfg5, true),
+                                MPR_CFG(Cfg6, false), MPR_CFG(Cfg6, true)};
 #undef MPR_CFG
 static constexpr int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 
