@@ -156,6 +156,15 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _vptr(t, n: int):
+    """Device pointer of an int64 vector of at least n entries (None -> NULL)."""
+    if t is None:
+        return None
+    if t.dtype != torch.int64 or t.dim() != 1 or (t.numel() > 1 and t.stride(0) != 1) or t.numel() < n:
+        raise ValueError("expected a contiguous int64 vector of at least %d entries" % n)
+    return _ptr(t)
+
+
 def _stream(stream):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -273,7 +282,7 @@ def normalise(C, R_in=None, R_out=None, check=True, stream=None):
     if R_out is None:
         R_out = torch.empty(M, dtype=torch.int64, device=C.device)
     st = _status_tensor(C.device) if check else None
-    _ok(lib().mpr_normalise(M, N, _ptr(C), _ld(C), _ptr(R_in), _ptr(R_out), _ptr(st), _stream(stream)),
+    _ok(lib().mpr_normalise(M, N, _ptr(C), _ld(C), _vptr(R_in, M), _vptr(R_out, M), _ptr(st), _stream(stream)),
         "mpr_normalise")
     if check:
         check_status(st)
@@ -292,8 +301,8 @@ def minplus_gemm_norm(A, B, Ra=None, Rb=None, C=None, Rc=None, ws=None, check=Tr
         _ok(lib().mpr_gemm_norm_workspace_size(K, N, ctypes.byref(nb)), "mpr_gemm_norm_workspace_size")
         ws = workspace(nb.value, A.device)
     st = _status_tensor(A.device) if check else None
-    _ok(lib().mpr_minplus_gemm_norm(M, N, K, _ptr(A), _ld(A), _ptr(Ra), _ptr(B), _ld(B), _ptr(Rb), _ptr(C),
-                                    _ld(C), _ptr(Rc), _ptr(ws), ws.numel(), _ptr(st), _stream(stream)),
+    _ok(lib().mpr_minplus_gemm_norm(M, N, K, _ptr(A), _ld(A), _vptr(Ra, M), _ptr(B), _ld(B), _vptr(Rb, K), _ptr(C),
+                                    _ld(C), _vptr(Rc, M), _ptr(ws), ws.numel(), _ptr(st), _stream(stream)),
         "mpr_minplus_gemm_norm")
     if check:
         check_status(st)
@@ -316,7 +325,7 @@ def minplus_power(A, e: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=N
     if ws is None:
         ws = workspace(power_workspace_size(n, e, schedule), A.device)
     st = d_status if d_status is not None else (_status_tensor(A.device) if check else None)
-    _ok(lib().mpr_minplus_power(_ptr(A), n, _ld(A), e, schedule, _ptr(N_out), _ld(N_out), _ptr(R_out),
+    _ok(lib().mpr_minplus_power(_ptr(A), n, _ld(A), e, schedule, _ptr(N_out), _ld(N_out), _vptr(R_out, n),
                                 _ptr(ws), ws.numel(), _ptr(st), _stream(stream)), "mpr_minplus_power")
     if check and d_status is None:
         check_status(st)
@@ -326,7 +335,7 @@ def minplus_power(A, e: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=N
 def trace_min(N, R, out=None, stream=None):
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=N.device)
-    _ok(lib().mpr_trace_min(_ptr(N), N.shape[0], _ld(N), _ptr(R), _ptr(out), _stream(stream)), "mpr_trace_min")
+    _ok(lib().mpr_trace_min(_ptr(N), N.shape[0], _ld(N), _vptr(R, N.shape[0]), _vptr(out, 1), _stream(stream)), "mpr_trace_min")
     return out
 
 
@@ -335,7 +344,7 @@ def trace_of_product(X, RX, Y, RY, out=None, stream=None):
         raise ValueError("X and Y must share a leading dimension")
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=X.device)
-    _ok(lib().mpr_trace_of_product(_ptr(X), _ptr(RX), _ptr(Y), _ptr(RY), X.shape[0], _ld(X), _ptr(out),
+    _ok(lib().mpr_trace_of_product(_ptr(X), _vptr(RX, X.shape[0]), _ptr(Y), _vptr(RY, X.shape[0]), X.shape[0], _ld(X), _vptr(out, 1),
                                    _stream(stream)), "mpr_trace_of_product")
     return out
 
@@ -387,7 +396,9 @@ def period_formula(mu: int, lam: int, c: int, traces):
 def _descs(chains):
     arr = (ChainDesc * len(chains))()
     for i, (A, e, N_out, R_out) in enumerate(chains):
-        arr[i] = ChainDesc(A.data_ptr(), A.shape[0], _ld(A), int(e), N_out.data_ptr(), _ld(N_out), R_out.data_ptr())
+        _ptr(A), _ptr(N_out)  # device tensors
+        arr[i] = ChainDesc(A.data_ptr(), A.shape[0], _ld(A), int(e), N_out.data_ptr(), _ld(N_out),
+                           _vptr(R_out, A.shape[0]).value)
     return arr
 
 

@@ -101,3 +101,21 @@ def test_product_path_has_no_oracle_import():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+def test_binding_rejects_mistyped_buffers(mpr):
+    """Offset vectors must be contiguous int64 of the right length and
+    matrices 2-D uint16 with unit column stride; anything else is refused on
+    the host before a pointer reaches the library."""
+    import torch
+
+    for bad in (torch.zeros(8, dtype=torch.int32), torch.zeros(4, dtype=torch.int64),
+                torch.zeros(16, dtype=torch.int64)[::2], torch.zeros((2, 4), dtype=torch.int64)):
+        with pytest.raises(ValueError):
+            mpr._vptr(bad, 8)
+    assert mpr._vptr(None, 8) is None
+    for bad in (torch.zeros((4, 4), dtype=torch.int16), torch.zeros((4, 8), dtype=torch.uint16)[:, ::2],
+                torch.zeros(16, dtype=torch.uint16)):
+        with pytest.raises(ValueError):
+            mpr._ld(bad)
+    assert mpr._ld(torch.zeros((4, 8), dtype=torch.uint16)[:, :5]) == 8
