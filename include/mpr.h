@@ -224,8 +224,11 @@ mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_hos
  * class hashes of all earlier powers stay on the host).  When traces_host
  * is not NULL it receives kmax + 1 int64 values, traces_host[k] = trace of
  * A^k for k = 1..kmax (the chain then always runs to kmax), else the search
- * stops at the first confirmed repeat.  SYNCHRONOUS on `stream`.  Returns
- * MPR_ENOTFOUND when no repeat is confirmed, MPR_EOVERFLOW on overflow. */
+ * stops at the first confirmed repeat.  When A^mu has no finite entry
+ * (a nilpotent A) every c fits and *c_host = 0.  SYNCHRONOUS on `stream`.
+ * Returns MPR_ENOTFOUND when no repeat is confirmed (also when no periodic
+ * regime exists, e.g. components of A with different mean cycle weights),
+ * MPR_EOVERFLOW on overflow. */
 mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax,
                            int64_t *mu_host, int64_t *lam_host, int64_t *c_host,
                            int64_t *traces_host, void *ws, size_t ws_bytes, mpr_stream stream);

@@ -309,6 +309,8 @@ def find_period(A, kmax: int, keep_gamma: bool = True):
         if key in seen:
             k0, R0 = seen[key]
             fin = R != INF
+            if not fin.any():  # no finite entry: A^(k0+lam) = c (x) A^k0 for every c; report 0
+                return k0, k - k0, 0, gam
             diffs = np.unique(R[fin] - R0[fin])
             if len(diffs) != 1:
                 raise AssertionError("class keys equal but offsets disagree")

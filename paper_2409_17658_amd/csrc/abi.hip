@@ -477,11 +477,15 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
                 if (hipMemcpyAsync(cmp, out3, sizeof(cmp), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
                     return MPR_EHIP;
-                if (cmp[0] == 0 && cmp[1] == cmp[2]) {
+                // same N and emptiness (cmp[0] == 0) and one offset shift over
+                // the non-empty rows; with no non-empty row at all every shift
+                // fits and c = 0 is reported
+                const bool no_rows = cmp[1] == MPR_ROW_NONE && cmp[2] == -MPR_ROW_NONE;
+                if (cmp[0] == 0 && (cmp[1] == cmp[2] || no_rows)) {
                     found = true;
                     mu = j;
                     lam = k - j;
-                    cval = cmp[1] == MPR_ROW_NONE ? 0 : cmp[1];
+                    cval = no_rows ? 0 : cmp[1];
                 }
             }
             if (!found) seen.emplace(h, k);

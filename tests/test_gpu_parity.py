@@ -370,6 +370,38 @@ def test_find_period_stops_early_without_traces(mpr):
     assert (mu, lam, c) == (16, 5, 12) and tr is None
 
 
+def _tiny_cases():
+    I = O.INF
+    cases = [np.array([[3]]), np.array([[I]]), np.array([[I, 1], [I, I]]), np.array([[I, 0], [5, I]]),
+             np.array([[2, I, I], [I, I, 1], [I, 4, I]])]
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        M = rng.integers(0, 6, (5, 5)).astype(np.int64)
+        M[rng.random((5, 5)) < 0.5] = I
+        cases.append(M)
+    return [c.astype(np.int64) for c in cases]
+
+
+def test_tiny_and_degenerate_powers_and_periods(mpr):
+    """1 x 1 up to 5 x 5 matrices: a single finite entry, all infinite, a
+    nilpotent pattern, a weighted 2-cycle, a self-loop beside a 2-cycle of
+    another mean (no periodic regime), random sparse ones: every power
+    schedule and both period searches against the oracle."""
+    for A in _tiny_cases():
+        print("tiny", A.shape, flush=True)
+        Ad = _dev(mpr, _u16(A))
+        for e in (1, 2, 3, 7):
+            Nr, Rr = O.power_chain(A, e)
+            for schedule in (mpr.CHAIN, mpr.SQUARE, mpr.CHAIN_SPARSE):
+                N, R = mpr.minplus_power(Ad, e, schedule)
+                assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), (A, e, schedule)
+        mu, lam, c, tr = O.find_period(A, 12)
+        for sparse in (False, True):
+            got = mpr.find_period(Ad, 12, traces=True, slots=8, sparse=sparse)
+            assert got[:3] == (mu, lam, c), (A.tolist(), got[:3], (mu, lam, c), sparse)
+            assert all(got[3][k] == tr[k] for k in tr), (A.tolist(), sparse)
+
+
 def test_find_period_not_found(mpr):
     A = mpr.build_transfer(6)
     mu, lam, c, tr = mpr.find_period(A, 10, traces=True)

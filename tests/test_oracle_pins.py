@@ -313,3 +313,44 @@ def test_entrywise_and_row_restricted_helpers():
     assert np.array_equal(Nr, N[rows]) and np.array_equal(Rr, R[rows])
     T = O.transfer(5)
     assert np.array_equal(O.transfer_rows(5, [0, 7, 286]), T[[0, 7, 286]])
+
+
+def _raw_period_brute(A, K=12):
+    """Least (mu, lam) and a c with A^(mu+lam) = c (x) A^mu, from raw powers
+    (the definition, no canonical forms); c = 0 when A^mu has no finite entry."""
+    P = {1: O.from_u16(O.to_u16(A)) if A.dtype == np.uint16 else A.astype(np.int64)}
+    for k in range(2, K + 1):
+        P[k] = O.minplus(P[k - 1], P[1])
+    for mu in range(1, K):
+        for lam in range(1, K - mu + 1):
+            X, Y = P[mu], P[mu + lam]
+            if not np.array_equal(X == O.INF, Y == O.INF):
+                continue
+            fin = X != O.INF
+            d = np.unique(Y[fin] - X[fin])
+            if len(d) == 0:
+                return mu, lam, 0
+            if len(d) == 1:
+                return mu, lam, int(d[0])
+    return None
+
+
+def test_find_period_degenerate_matrices():
+    """Pins the period search on tiny and degenerate matrices against the
+    definition on raw powers: a single finite entry, all infinite, a
+    nilpotent pattern (powers become all infinite: any c fits, 0 reported),
+    a weighted 2-cycle (period 2), a self-loop beside a 2-cycle of another
+    mean weight (no periodic regime), and small random ones."""
+    I = O.INF
+    cases = [np.array([[3]]), np.array([[I]]), np.array([[I, 1], [I, I]]), np.array([[I, 0], [5, I]]),
+             np.array([[2, I, I], [I, I, 1], [I, 4, I]])]
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        M = rng.integers(0, 6, (4, 4)).astype(np.int64)
+        M[rng.random((4, 4)) < 0.5] = I
+        cases.append(M)
+    for A in cases:
+        A = A.astype(np.int64)
+        want = _raw_period_brute(A) or (None, None, None)  # none: components with different cycle means
+        mu, lam, c, _ = O.find_period(A, 12)
+        assert (mu, lam, c) == want, (A.tolist(), (mu, lam, c), want)
