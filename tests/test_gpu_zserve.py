@@ -64,3 +64,15 @@ def test_server_rejects_bad_queries(serve):
         r = S.query(1, 50)
         assert r["status"] == 0 and r["gamma"] == math.ceil(2 * 50 / 3)
         assert S.query(9, 10)["status"] == 2  # its ladder exceeds the 1 GiB budget
+
+
+def test_server_ladder_boundaries(serve):
+    """Queries on the seams of the ladder: n <= B read off the baby traces,
+    n = B (the first giant), B + 1, 2B, 2B + 1 and n = max_n, for m = 1..4."""
+    B, max_n = 8, 41
+    ns = [3, 4, B - 1, B, B + 1, 2 * B, 2 * B + 1, max_n - 1, max_n]
+    with serve.Server(baby=B, max_n=max_n, max_batch=16, slots=2, hbm_budget_bytes=1 << 30) as S:
+        for m in (1, 2, 3, 4):
+            for n in ns:
+                r = S.query(m, n)
+                assert r["status"] == 0 and r["gamma"] == oracle_gamma(m, n), (m, n, r)
