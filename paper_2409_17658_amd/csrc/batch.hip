@@ -332,6 +332,14 @@ static double lpt_makespan(const std::vector<double> &work_sorted, int slots)
     return *std::max_element(heap.begin(), heap.end());
 }
 
+// Relative throughput of each configuration on a full chip (uniform
+// batches of 128 chains of N = 1024, e = 17, measured on MI355X; the f16
+// 64x128 4x8 configuration = 1).  The schedule model below scores load
+// balance; these weigh in how fast each tile shape runs.
+static const double kBatchRel[] = {0.80, 0.68, 0.77, 0.61, 0.57, 0.72,   // uint16 0..5
+                                   1.00, 0.84, 0.97, 0.76, 0.69, 0.89};  // f16 6..11
+static_assert(sizeof(kBatchRel) / sizeof(kBatchRel[0]) == kNumBatchCfgs, "one prior per configuration");
+
 static int choose_batch_cfg(const mpr_chain_desc *d, int count)
 {
     const int cus = device_cu_count();
@@ -345,11 +353,10 @@ static int choose_batch_cfg(const mpr_chain_desc *d, int count)
                 w.push_back((double)(d[i].e - 1) * (double)std::min<int64_t>(bm, d[i].n - r0) * (double)d[i].n *
                             (double)d[i].n);
         std::sort(w.begin(), w.end(), std::greater<double>());
-        // A worker's speed is the CU's rate shared among its resident workers;
-        // the f16 form issues 3 instructions where the uint16 form issues 4.
+        // A worker's speed is the CU's rate (kBatchRel) shared among its
+        // resident workers.
         const int per_cu = std::max(1, occupancy(c));
-        const double rate = kBatchCfgs[c].arith == MPR_ARITH_F16 ? 0.75 : 1.0;
-        const double t = lpt_makespan(w, cus * per_cu) * per_cu * rate;
+        const double t = lpt_makespan(w, cus * per_cu) * per_cu / kBatchRel[c];
         if (t < best_t) {
             best_t = t;
             best = c;
