@@ -277,22 +277,25 @@ __device__ __forceinline__ void tile_kloop(int64_t nk, AOp &aop, BOp &bop, u16 *
 }
 
 // Converts the accumulators of an f16 pass back to uint16 (+inf -> 0xFFFF)
-// and returns true when one of them is not exact (finite, >= 0x800).
+// and returns true when one of them is not exact (finite, >= 0x800).  All
+// packed: v + 0x8400 (wrapping) takes +inf to 0, the exact values below
+// 0x800 to [0x8400, 0x8BFF] and the inexact ones to [0x8C00, 0xFFFF]; among
+// the values kept only +inf has bit 14 set, which the shift pair spreads
+// over the half.
 template <class T>
 __device__ __forceinline__ bool tile_from_h16(TileAcc<T> &acc)
 {
-    bool redo = false;
+    u16x2 worst = {0, 0};
 #pragma unroll
     for (int r = 0; r < T::TM; r++)
 #pragma unroll
         for (int c = 0; c < T::NACC; c++) {
-            u16x2 v = acc.v[r][c];
-            redo |= (v.x >= 0x800 && v.x != 0x7C00) || (v.y >= 0x800 && v.y != 0x7C00);
-            v.x = v.x == 0x7C00 ? (u16)0xFFFF : v.x;
-            v.y = v.y == 0x7C00 ? (u16)0xFFFF : v.y;
-            acc.v[r][c] = v;
+            const u16x2 v = acc.v[r][c];
+            worst = __builtin_elementwise_max(worst, v + (u16x2){0x8400, 0x8400});
+            const i16x2 hi = __builtin_bit_cast(i16x2, v << (u16)1) >> (short)15;
+            acc.v[r][c] = v | __builtin_bit_cast(u16x2, hi);
         }
-    return redo;
+    return worst.x >= 0x8C00 || worst.y >= 0x8C00;
 }
 
 // The (min,+) block product: form H, with the uint16 recomputation for the
