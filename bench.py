@@ -430,18 +430,21 @@ def bench_config4(args, mpr, torch):
     ws = mpr.workspace(mpr.batch_workspace_size(chains))
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     stream = torch.cuda.Stream()
-    # autotune: time one launch per batched configuration
+    # autotune: time one launch per batched configuration (or take the one given)
     tune = {}
-    for cfg in range(mpr.batch_config_count()):
-        mpr.set_batch_config(cfg)
-        mpr.batch_plan(chains, ws, stream)
-        t0 = time.perf_counter()
-        mpr.batch_launch(ws, st, stream)
-        stream.synchronize()
-        tune[cfg] = time.perf_counter() - t0
-    best = min(tune, key=tune.get)
-    mpr.set_batch_config(best)
+    if args.batch_cfg == -2:
+        for cfg in range(mpr.batch_config_count()):
+            mpr.set_batch_config(cfg)
+            mpr.batch_plan(chains, ws, stream)
+            t0 = time.perf_counter()
+            mpr.batch_launch(ws, st, stream)
+            stream.synchronize()
+            tune[cfg] = time.perf_counter() - t0
+        mpr.set_batch_config(min(tune, key=tune.get))
+    else:
+        mpr.set_batch_config(args.batch_cfg)
     mpr.batch_plan(chains, ws, stream)
+    best = mpr.batch_plan_info(ws)[0]
     g = mpr.batch_graph_create(ws, st, stream)
     mpr.graph_launch(g, stream)
     stream.synchronize()
@@ -456,16 +459,18 @@ def bench_config4(args, mpr, torch):
     mpr.check_status(st)
     batched = [(N.clone(), R.clone()) for (_, _, N, R) in chains]
     # the plain per-instance path: one chain after another
-    wsi = mpr.workspace(max(mpr.power_workspace_size(d["n"], d["e"], mpr.CHAIN) for d in inst))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for (A, e, N, R) in chains:
-        mpr.minplus_power(A, e, mpr.CHAIN, N, R, wsi, check=False, d_status=st)
-    torch.cuda.synchronize()
-    t_solo = time.perf_counter() - t0
-    mpr.check_status(st)
-    same = all(torch.equal(N.view(torch.int16), b[0].view(torch.int16)) and torch.equal(R, b[1])
-               for (_, _, N, R), b in zip(chains, batched))
+    t_solo, same = None, None
+    if args.per_instance:
+        wsi = mpr.workspace(max(mpr.power_workspace_size(d["n"], d["e"], mpr.CHAIN) for d in inst))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (A, e, N, R) in chains:
+            mpr.minplus_power(A, e, mpr.CHAIN, N, R, wsi, check=False, d_status=st)
+        torch.cuda.synchronize()
+        t_solo = time.perf_counter() - t0
+        mpr.check_status(st)
+        same = all(torch.equal(N.view(torch.int16), b[0].view(torch.int16)) and torch.equal(R, b[1])
+                   for (_, _, N, R), b in zip(chains, batched))
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     binfo = mpr.batch_config_info(best)
     return {"metric": "batched min-plus power chains GOPS (256 chains, one persistent launch in a HIP graph)",
@@ -475,12 +480,12 @@ def bench_config4(args, mpr, torch):
                        "total_pairs": pairs, "batch_config": best, "panel_rows": binfo["panel_rows"],
                        "per_instance_tile_configs": sorted({mpr.gemm_pick_config(d["n"], d["n"], d["n"])
                                                             for d in inst})},
-            "batched_s": round(t_batch, 3), "per_instance_s": round(t_solo, 3),
-            "per_instance_gpairs": round(pairs / t_solo / 1e9, 1),
-            "speedup_vs_per_instance": round(t_solo / t_batch, 2),
+            "batched_s": round(t_batch, 3), "per_instance_s": round(t_solo, 3) if t_solo else None,
+            "per_instance_gpairs": round(pairs / t_solo / 1e9, 1) if t_solo else None,
+            "speedup_vs_per_instance": round(t_solo / t_batch, 2) if t_solo else None,
             "pct_valu_peak": round(100 * pairs / t_batch / 1e9 / valu_peak_gpairs(cus, binfo["arith"]), 2),
             "autotune_s": {str(k): round(v, 3) for k, v in tune.items()},
-            "batched_equals_per_instance": bool(same), "input_gen_s": round(gen_s, 1)}
+            "batched_equals_per_instance": None if same is None else bool(same), "input_gen_s": round(gen_s, 1)}
 
 
 # ---------------------------------------------------------------- config 5
@@ -544,6 +549,10 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-prewarm", type=int, default=1)
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--batch-cfg", type=int, default=-2,
+                    help="config4: batched configuration (-2: time every one and keep the fastest, "
+                         "-1: the library's schedule model)")
+    ap.add_argument("--per-instance", type=int, default=1, help="config4: also time the per-instance path")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (scale for the HBM byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "gemm_traffic.json"))
