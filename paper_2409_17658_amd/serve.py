@@ -23,6 +23,7 @@ class Server:
             raise MprError(st, "mpr_server_create")
         self.h = h
         self._buf = (QueryResult * 1024)()
+        self._held = []  # results query() read while waiting for its own
 
     def submit(self, m: int, n: int, tag: int):
         st = lib().mpr_server_submit(self.h, m, n, tag)
@@ -30,6 +31,12 @@ class Server:
             raise MprError(st, "mpr_server_submit")
 
     def poll(self, wait_ms: int = 10):
+        if self._held:
+            out, self._held = self._held, []
+            return out
+        return self._poll(wait_ms)
+
+    def _poll(self, wait_ms: int):
         cnt = ctypes.c_int()
         st = lib().mpr_server_poll(self.h, self._buf, len(self._buf), ctypes.byref(cnt), wait_ms)
         if st != 0:
@@ -50,14 +57,16 @@ class Server:
         return {k: getattr(s, k) for k, _ in ServerStats._fields_}
 
     def query(self, m: int, n: int, timeout_s: float = 600.0) -> dict:
-        """One request alone: submit and wait for its answer."""
+        """Submit one request and wait for its answer; other results that
+        arrive meanwhile are kept for the next poll()."""
         tag = int(time.monotonic_ns() & 0x7FFFFFFFFFFF)
         self.submit(m, n, tag)
         t_end = time.monotonic() + timeout_s
         while time.monotonic() < t_end:
-            for r in self.poll(50):
+            for r in self._poll(50):
                 if r["tag"] == tag:
                     return r
+                self._held.append(r)  # someone else's: returned by the next poll()
         raise TimeoutError("query (%d, %d) did not complete" % (m, n))
 
     def close(self):

@@ -2,6 +2,7 @@
 the same when the query runs alone and when it runs inside a Poisson mix
 (tolerance 0); a tiny HBM budget forces admission waits and evictions."""
 import math
+import time
 
 import pytest
 
@@ -76,3 +77,15 @@ def test_server_ladder_boundaries(serve):
             for n in ns:
                 r = S.query(m, n)
                 assert r["status"] == 0 and r["gamma"] == oracle_gamma(m, n), (m, n, r)
+
+
+def test_query_keeps_other_results(serve):
+    """A result that arrives while query() waits for its own is handed to
+    the next poll(), not dropped."""
+    with serve.Server(baby=8, max_n=40, max_batch=8, slots=2, hbm_budget_bytes=1 << 30) as S:
+        S.submit(3, 17, 4242)
+        time.sleep(0.2)  # let it complete first
+        r = S.query(3, 18)
+        assert r["gamma"] == oracle_gamma(3, 18)
+        held = S.poll(1000)
+        assert [h["tag"] for h in held] == [4242] and held[0]["gamma"] == oracle_gamma(3, 17)
