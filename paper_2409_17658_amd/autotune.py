@@ -18,7 +18,7 @@ from . import autotune_gemm, gemm_config_count, gemm_config_info, init, set_tile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tile_table.json")
-DEFAULT_SIZES = (64, 256, 848, 1536, 2507, 4096, 7411, 8192, 16384)
+DEFAULT_SIZES = (64, 256, 512, 848, 1024, 1536, 2048, 2507, 3072, 4096, 6144, 7411, 8192, 12288, 16384)
 
 
 def tune(sizes=DEFAULT_SIZES, reps: int = 3, path: str = TABLE) -> dict:
