@@ -473,7 +473,7 @@ def bench_config4(args, mpr, torch):
                    for (_, _, N, R), b in zip(chains, batched))
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     binfo = mpr.batch_config_info(best)
-    return {"metric": "batched min-plus power chains GOPS (256 chains, one persistent launch in a HIP graph)",
+    return {"metric": "batched min-plus power chains GOPS (256 chains, one launch in a HIP graph)",
             "value": round(pairs / t_batch / 1e9, 1), "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
             "dtype": binfo["arith"], "data": "synthetic (batch_instances seed 4; entries U[0,31], 25% infinity)",
             "config": {"workload": "256 chains, N log-uniform [256,4096], e uniform [8,128]",

@@ -256,7 +256,7 @@ mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t lda, int64_t
                               void *ws, size_t ws_bytes, mpr_stream stream);
 
 /* ------------------------------------------------------------------ */
-/* Batched power chains: one persistent launch.                        */
+/* Batched power chains: one launch.                                   */
 /* ------------------------------------------------------------------ */
 
 typedef struct {
@@ -274,21 +274,21 @@ mpr_status mpr_batch_workspace_size(const mpr_chain_desc *descs_host, int count,
 
 /* Plans a batch into the workspace: splits every chain into row panels
  * (row i of A^k depends only on row i of A^(k-1) and on A, so panels never
- * wait on each other), orders the panels longest first and uploads the
- * work list.  Synchronous.  The workspace then holds the whole launch
+ * wait on each other), orders the panels longest first (a ragged last
+ * panel costs as much as a full one) and uploads the work list.  Synchronous.  The workspace then holds the whole launch
  * state; mpr_batch_launch may be called (or captured) any number of times. */
 mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count,
                           void *ws, size_t ws_bytes, mpr_stream stream);
 
 /* Runs a planned batch: resets the work counter with a fill kernel and
- * launches the persistent kernel (no memset node, no host sync, so the pair
- * can be captured into a HIP graph).  Results land in each N_out / R_out. */
+ * launches one workgroup per panel, the k-th workgroup to start taking the
+ * k-th longest panel (no memset node, no host sync, so the pair can be
+ * captured into a HIP graph).  Results land in each N_out / R_out. */
 mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream stream);
 
-/* Describes the plan held in ws: configuration, workgroups of the
- * persistent grid (resident workgroups per CU x CUs, at most the number of
- * panels) and number of panels (host ints, any may be NULL).  MPR_EINVAL if
- * ws holds no plan. */
+/* Describes the plan held in ws: configuration, workgroups of the grid
+ * (one per panel) and number of panels (host ints, any may be NULL).
+ * MPR_EINVAL if ws holds no plan. */
 mpr_status mpr_batch_plan_info(void *ws, int *cfg, int *grid, int *panels);
 
 /* Plan + launch. */

@@ -462,7 +462,7 @@ def set_sparse_arith(arith: str):
 
 
 def batch_plan_info(ws):
-    """(configuration, persistent-grid workgroups, panels) of the plan in ws."""
+    """(configuration, workgroups of the grid, panels) of the plan in ws."""
     v = [ctypes.c_int() for _ in range(3)]
     _ok(lib().mpr_batch_plan_info(_ptr(ws), *[ctypes.byref(x) for x in v]), "mpr_batch_plan_info")
     return tuple(x.value for x in v)

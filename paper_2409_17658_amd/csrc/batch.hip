@@ -1,13 +1,20 @@
-// batch.hip -- many independent power chains in one persistent launch.
+// batch.hip -- many independent power chains in one launch.
 //
 // Row i of A^k = A^(k-1) (x) A depends only on row i of A^(k-1) and on A, and
 // the row-min normalisation is per row, so a block of rows (a "panel") of one
 // chain can run all of its e-1 steps without ever waiting for another
 // panel.  The batch is cut into panels of BM rows; a work list of
-// (instance, first row) items, longest first, is consumed by a grid sized to
-// the number of resident workgroups, each pulling the next item with one
-// atomic add.  Every workgroup leaves the loop once the list is exhausted,
-// so the grid always drains.  Per step, a panel computes its BM x n slice of
+// (instance, first row) items, longest first, is consumed by a grid of one
+// workgroup per item, each taking the next item with one atomic add when it
+// starts, so the k-th workgroup to start runs the k-th longest item.  The
+// grid is not persistent on purpose: the CU's wave arbiter favours older
+// waves, so of the workgroups sharing a CU the youngest ones progress
+// slowest (on MI355X, four resident workgroups of the 64-row f16
+// configuration ran at 123, 45, 22 and 16 G pairs/s).  A persistent
+// workgroup never gets older than its neighbours, so the ones that started
+// last kept their long first items to the very end of the launch; with one
+// workgroup per item the oldest waves hold the longest items and the
+// youngest the shortest.  Per step, a panel computes its BM x n slice of
 // the raw product column tile by column tile (the shared tile routine),
 // keeps the running row minima in LDS, then rewrites the slice normalised.
 // Only workgroup barriers separate the phases: no data crosses workgroups.
@@ -131,119 +138,116 @@ struct BatchWaves {
 
 template <class T, bool H>
 __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<T>::value)))
-void batch_kernel(const DevChain *__restrict__ chains,
-                                                      const BatchItem *__restrict__ items, int n_items,
-                                                      int *counter, int32_t *st)
+void batch_kernel(const DevChain *__restrict__ chains, const BatchItem *__restrict__ items, int n_items,
+                  int *counter, int32_t *st)
 {
     __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
     __shared__ uint32_t rmin[T::BM];
     __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = next;
-        __syncthreads();
-        if (it >= n_items) break;
-        const BatchItem item = items[it];
-        const DevChain c = chains[item.inst];
-        const int64_t n = c.n, r0 = item.row0;
-        const int rows = (int)min<int64_t>(T::BM, n - r0);
-        // Step k writes buffer (e - k) % 2 so that step e lands in N_out.
-        u16 *buf[2] = {c.N_out, c.P};
-        const int64_t ld[2] = {c.ldo, c.ldp};
-        int b = (int)((c.e - 1) & 1);
+    // One workgroup per item: the k-th workgroup to start takes the k-th
+    // longest item.
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    if (it >= n_items) return;  // block-uniform; not taken when the grid is the item count
+    const BatchItem item = items[it];
+    const DevChain c = chains[item.inst];
+    const int64_t n = c.n, r0 = item.row0;
+    const int rows = (int)min<int64_t>(T::BM, n - r0);
+    // Step k writes buffer (e - k) % 2 so that step e lands in N_out.
+    u16 *buf[2] = {c.N_out, c.P};
+    const int64_t ld[2] = {c.ldo, c.ldp};
+    int b = (int)((c.e - 1) & 1);
 
-        const bool vec = ((uintptr_t)c.A % 16 == 0) && c.lda % 8 == 0 && ((uintptr_t)c.N_out % 16 == 0) &&
-                         c.ldo % 8 == 0 && ((uintptr_t)c.P % 16 == 0) && c.ldp % 8 == 0;
-        // Step 1: the panel of A itself, normalised.
+    const bool vec = ((uintptr_t)c.A % 16 == 0) && c.lda % 8 == 0 && ((uintptr_t)c.N_out % 16 == 0) &&
+                     c.ldo % 8 == 0 && ((uintptr_t)c.P % 16 == 0) && c.ldp % 8 == 0;
+    // Step 1: the panel of A itself, normalised.
+    for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
+    __syncthreads();
+    panel_rowmin<T::NT>(c.A, c.lda, r0, rows, n, rmin, vec);
+    __syncthreads();
+    panel_normalise<T::NT>(c.A, c.lda, buf[b], ld[b], r0, rows, n, rmin, c.R_out, true, vec, st);
+
+    for (int64_t k = 2; k <= c.e; k++) {
+        __syncthreads();
+        const int nb = b ^ 1;
         for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
-        __syncthreads();
-        panel_rowmin<T::NT>(c.A, c.lda, r0, rows, n, rmin, vec);
-        __syncthreads();
-        panel_normalise<T::NT>(c.A, c.lda, buf[b], ld[b], r0, rows, n, rmin, c.R_out, true, vec, st);
-
-        for (int64_t k = 2; k <= c.e; k++) {
-            __syncthreads();
-            const int nb = b ^ 1;
-            for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
-            // (visibility of rmin is covered by the barriers inside the tile loop)
-            // 32-bit offsets: n <= 32768 and leading dimensions <= 65528.
-            const gu16 *Lp = glob(buf[b]) + r0 * ld[b];
-            gu16 *Op = glob(buf[nb]) + r0 * ld[nb];
-            const gu16 *Ap = glob(c.A);
-            const int ldl = (int)ld[b], ldo = (int)ld[nb], lda = (int)c.lda, nn = (int)n;
-            for (int n0 = 0; n0 < nn; n0 += T::BN) {
-                TileAcc<T> acc;
-                // Left operand: rows r0.. of the previous power (rows beyond
-                // `rows` read as infinity); right operand: A.
-                tile_mainloop_with<T, H>(
-                    (nn + T::BK - 1) / T::BK,
-                    [&](int64_t k0, int row, int kc) {
-                        const int k = (int)k0 + kc;
-                        if (vec && row < rows && k + 8 <= nn) return gload16(Lp + (row * ldl + k));
-                        uint32_t w[4];
+        // (visibility of rmin is covered by the barriers inside the tile loop)
+        // 32-bit offsets: n <= 32768 and leading dimensions <= 65528.
+        const gu16 *Lp = glob(buf[b]) + r0 * ld[b];
+        gu16 *Op = glob(buf[nb]) + r0 * ld[nb];
+        const gu16 *Ap = glob(c.A);
+        const int ldl = (int)ld[b], ldo = (int)ld[nb], lda = (int)c.lda, nn = (int)n;
+        for (int n0 = 0; n0 < nn; n0 += T::BN) {
+            TileAcc<T> acc;
+            // Left operand: rows r0.. of the previous power (rows beyond
+            // `rows` read as infinity); right operand: A.
+            tile_mainloop_with<T, H>(
+                (nn + T::BK - 1) / T::BK,
+                [&](int64_t k0, int row, int kc) {
+                    const int k = (int)k0 + kc;
+                    if (vec && row < rows && k + 8 <= nn) return gload16(Lp + (row * ldl + k));
+                    uint32_t w[4];
 #pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            const uint32_t lo = (row < rows && k + 2 * q < nn) ? Lp[row * ldl + k + 2 * q] : 0xFFFFu;
-                            const uint32_t hi =
-                                (row < rows && k + 2 * q + 1 < nn) ? Lp[row * ldl + k + 2 * q + 1] : 0xFFFFu;
-                            w[q] = lo | (hi << 16);
-                        }
-                        return make_uint4(w[0], w[1], w[2], w[3]);
-                    },
-                    [&](int64_t k0, int kr, int jc) {
-                        const int k = (int)k0 + kr, j = n0 + jc;
-                        if (vec && k < nn && j + 8 <= nn) return gload16(Ap + (k * lda + j));
-                        uint32_t w[4];
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            const uint32_t lo = (k < nn && j + 2 * q < nn) ? Ap[k * lda + j + 2 * q] : 0xFFFFu;
-                            const uint32_t hi = (k < nn && j + 2 * q + 1 < nn) ? Ap[k * lda + j + 2 * q + 1] : 0xFFFFu;
-                            w[q] = lo | (hi << 16);
-                        }
-                        return make_uint4(w[0], w[1], w[2], w[3]);
-                    },
-                    lds, acc);
-#pragma unroll
-                for (int r = 0; r < T::TM; r++) {
-                    const int row = tile_row<T>(r);
-                    if (row >= rows) continue;
-#pragma unroll
-                    for (int c8 = 0; c8 < T::TN / 8; c8++) {
-                        const int col = n0 + tile_col<T>(c8);
-                        const uint4 v = make_uint4(as_u32(acc.v[r][c8 * 4 + 0]), as_u32(acc.v[r][c8 * 4 + 1]),
-                                                   as_u32(acc.v[r][c8 * 4 + 2]), as_u32(acc.v[r][c8 * 4 + 3]));
-                        if (vec && col + 8 <= nn) {
-                            gstore16(Op + (row * ldo + col), v);
-                        } else {
-                            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                            for (int e = 0; e < 8; e++)
-                                if (col + e < nn) Op[row * ldo + col + e] = (u16)(w[e >> 1] >> ((e & 1) * 16));
-                        }
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t lo = (row < rows && k + 2 * q < nn) ? Lp[row * ldl + k + 2 * q] : 0xFFFFu;
+                        const uint32_t hi =
+                            (row < rows && k + 2 * q + 1 < nn) ? Lp[row * ldl + k + 2 * q + 1] : 0xFFFFu;
+                        w[q] = lo | (hi << 16);
                     }
-                }
+                    return make_uint4(w[0], w[1], w[2], w[3]);
+                },
+                [&](int64_t k0, int kr, int jc) {
+                    const int k = (int)k0 + kr, j = n0 + jc;
+                    if (vec && k < nn && j + 8 <= nn) return gload16(Ap + (k * lda + j));
+                    uint32_t w[4];
 #pragma unroll
-                for (int r = 0; r < T::TM; r++) {
-                    uint32_t m = 0xFFFFu;
-#pragma unroll
-                    for (int q = 0; q < T::NACC; q++) {
-                        const uint32_t w = as_u32(acc.v[r][q]);
-                        const int col = tile_col<T>(q >> 2) + 2 * (q & 3);
-                        if (n0 + col < n) m = min(m, w & 0xFFFFu);
-                        if (n0 + col + 1 < n) m = min(m, w >> 16);
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t lo = (k < nn && j + 2 * q < nn) ? Ap[k * lda + j + 2 * q] : 0xFFFFu;
+                        const uint32_t hi = (k < nn && j + 2 * q + 1 < nn) ? Ap[k * lda + j + 2 * q + 1] : 0xFFFFu;
+                        w[q] = lo | (hi << 16);
                     }
-                    // lanes tx = 0..TX-1 of one row group are consecutive
+                    return make_uint4(w[0], w[1], w[2], w[3]);
+                },
+                lds, acc);
 #pragma unroll
-                    for (int off = 1; off < T::TX; off <<= 1) m = min(m, (uint32_t)__shfl_xor(m, off, 64));
-                    if (threadIdx.x % T::TX == 0) atomicMin(&rmin[tile_row<T>(r)], m);
+            for (int r = 0; r < T::TM; r++) {
+                const int row = tile_row<T>(r);
+                if (row >= rows) continue;
+#pragma unroll
+                for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                    const int col = n0 + tile_col<T>(c8);
+                    const uint4 v = make_uint4(as_u32(acc.v[r][c8 * 4 + 0]), as_u32(acc.v[r][c8 * 4 + 1]),
+                                               as_u32(acc.v[r][c8 * 4 + 2]), as_u32(acc.v[r][c8 * 4 + 3]));
+                    if (vec && col + 8 <= nn) {
+                        gstore16(Op + (row * ldo + col), v);
+                    } else {
+                        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int e = 0; e < 8; e++)
+                            if (col + e < nn) Op[row * ldo + col + e] = (u16)(w[e >> 1] >> ((e & 1) * 16));
+                    }
                 }
             }
-            __syncthreads();
-            panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, vec, st);
-            b = nb;
+#pragma unroll
+            for (int r = 0; r < T::TM; r++) {
+                uint32_t m = 0xFFFFu;
+#pragma unroll
+                for (int q = 0; q < T::NACC; q++) {
+                    const uint32_t w = as_u32(acc.v[r][q]);
+                    const int col = tile_col<T>(q >> 2) + 2 * (q & 3);
+                    if (n0 + col < n) m = min(m, w & 0xFFFFu);
+                    if (n0 + col + 1 < n) m = min(m, w >> 16);
+                }
+                // lanes tx = 0..TX-1 of one row group are consecutive
+#pragma unroll
+                for (int off = 1; off < T::TX; off <<= 1) m = min(m, (uint32_t)__shfl_xor(m, off, 64));
+                if (threadIdx.x % T::TX == 0) atomicMin(&rmin[tile_row<T>(r)], m);
+            }
         }
         __syncthreads();
+        panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, vec, st);
+        b = nb;
     }
 }
 
@@ -332,12 +336,20 @@ static double lpt_makespan(const std::vector<double> &work_sorted, int slots)
     return *std::max_element(heap.begin(), heap.end());
 }
 
+// Modelled cost of one panel: the tile routine computes all BM rows of a
+// panel (rows past the end of the matrix read as infinity), so a ragged last
+// panel costs as much as a full one and is ordered with them.
+static double panel_cost(const mpr_chain_desc &d, int bm)
+{
+    return (double)d.e * (double)bm * (double)d.n * (double)d.n;
+}
+
 // Relative throughput of each configuration on a full chip (uniform
 // batches of 128 chains of N = 1024, e = 17, measured on MI355X; the f16
 // 64x128 4x8 configuration = 1).  The schedule model below scores load
 // balance; these weigh in how fast each tile shape runs.
-static const double kBatchRel[] = {0.80, 0.68, 0.77, 0.61, 0.57, 0.72,   // uint16 0..5
-                                   1.00, 0.84, 0.97, 0.76, 0.69, 0.89};  // f16 6..11
+static const double kBatchRel[] = {0.79, 0.63, 0.75, 0.69, 0.49, 0.70,   // uint16 0..5
+                                   1.00, 0.77, 0.93, 0.86, 0.63, 0.88};  // f16 6..11
 static_assert(sizeof(kBatchRel) / sizeof(kBatchRel[0]) == kNumBatchCfgs, "one prior per configuration");
 
 static int choose_batch_cfg(const mpr_chain_desc *d, int count)
@@ -349,9 +361,7 @@ static int choose_batch_cfg(const mpr_chain_desc *d, int count)
         const int bm = kBatchCfgs[c].bm;
         std::vector<double> w;
         for (int i = 0; i < count; i++)
-            for (int64_t r0 = 0; r0 < d[i].n; r0 += bm)
-                w.push_back((double)(d[i].e - 1) * (double)std::min<int64_t>(bm, d[i].n - r0) * (double)d[i].n *
-                            (double)d[i].n);
+            for (int64_t r0 = 0; r0 < d[i].n; r0 += bm) w.push_back(panel_cost(d[i], bm));
         std::sort(w.begin(), w.end(), std::greater<double>());
         // A worker's speed is the CU's rate (kBatchRel) shared among its
         // resident workers.
@@ -427,10 +437,7 @@ extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count
     for (int i = 0; i < count; i++) {
         const mpr_chain_desc &d = descs_host[i];
         chains[i] = DevChain{d.A, d.n, d.lda, d.e, d.N_out, d.ldo, d.R_out, (u16 *)(base + L.buf_off[i]), L.ldp[i]};
-        for (int64_t r0 = 0; r0 < d.n; r0 += bm) {
-            const double w = (double)(d.e - 1 + 1) * (double)std::min<int64_t>(bm, d.n - r0) * (double)d.n * (double)d.n;
-            items.push_back({w, BatchItem{i, (int32_t)r0}});
-        }
+        for (int64_t r0 = 0; r0 < d.n; r0 += bm) items.push_back({panel_cost(d, bm), BatchItem{i, (int32_t)r0}});
     }
     std::stable_sort(items.begin(), items.end(),
                      [](const std::pair<double, BatchItem> &a, const std::pair<double, BatchItem> &b) {
@@ -449,7 +456,7 @@ extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count
     BatchPlan plan;
     plan.cfg = cfg;
     plan.n_items = (int)flat.size();
-    plan.grid = std::max(1, std::min(plan.n_items, device_cu_count() * occupancy(cfg)));
+    plan.grid = std::max(1, plan.n_items);
     plan.chains = (DevChain *)(base + L.chains_off);
     plan.items = (BatchItem *)(base + L.items_off);
     plan.counter = (int *)(base + L.counter_off);

@@ -1,5 +1,5 @@
 // tile.h -- the (min,+) tile routine shared by the single-product kernel and
-// the persistent batched kernel.
+// the batched kernel.
 //
 // One workgroup computes a BM x BN block of C = A (x) B (Section 3:
 // c_ij = min_k a_ik + b_kj).  K is walked in BK-deep slices that are copied

@@ -1,4 +1,4 @@
-"""Batched power chains (one persistent launch) against the oracle, against
+"""Batched power chains (one launch) against the oracle, against
 the same chains run one at a time, and across HIP graph replays."""
 import numpy as np
 import pytest
