@@ -324,22 +324,22 @@ mpr_status fill_i32_launch(int32_t *p, int64_t count, int32_t v, hipStream_t s)
 // RX[i] + X[i][l] + RY[l] + Y[l][i], one tile per block (trace_tile.h).
 __global__ __launch_bounds__(256) void trace_product_kernel(const u16 *X, const int64_t *RX, const u16 *Y,
                                                             const int64_t *RY, int64_t n, int64_t ld, int64_t *out,
-                                                            int vec)
+                                                            int vec, int chunk)
 {
-    // Grid-stride over the tiles with a running minimum and ONE atomic per
-    // block at the end: an atomic per tile on the one result word would
-    // serialise (over 100k of them at N = 21909).
+    // `chunk` consecutive tiles per block, a running minimum, and one fold
+    // into the result word per block.
     __shared__ TPShared sh;
     const int64_t tiles = (n + TPI - 1) / TPI, total = tiles * tiles;
+    const int64_t t0 = (int64_t)blockIdx.x * chunk, t1 = t0 + chunk < total ? t0 + chunk : total;
     int64_t best = ROW_NONE;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    for (int64_t t = t0; t < t1; t++) {
         int64_t ti, tl;
         tp_tile_of(t, tiles, ti, tl);
         const int64_t v = tp_tile(X, RX, Y, RY, n, ld, ti * TPI, tl * TPL, vec != 0, sh);
         best = v < best ? v : best;
         __syncthreads();  // the next tile reuses sh
     }
-    if (threadIdx.x == 0 && best != ROW_NONE) atomicMin((long long *)out, (long long)best);
+    if (threadIdx.x == 0) tp_fold_min(out, best);
 }
 
 mpr_status trace_product_launch(const u16 *X, const int64_t *RX, const u16 *Y, const int64_t *RY, int64_t n,
@@ -351,8 +351,10 @@ mpr_status trace_product_launch(const u16 *X, const int64_t *RX, const u16 *Y, c
     if (e != MPR_OK || n == 0) return e;
     const int64_t tiles = (n + TPI - 1) / TPI;
     const int vec = aligned16(X) && aligned16(Y) && ld % 8 == 0;
-    const int64_t grid = std::min<int64_t>(tiles * tiles, (int64_t)device_cu_count() * TP_BLOCKS_PER_CU);
-    hipLaunchKernelGGL(trace_product_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, RX, Y, RY, n, ld, out, vec);
+    const int64_t grid = tp_blocks(tiles);  // <= 2^18 for n <= 65536
+    if (grid > INT32_MAX) return MPR_EUNSUPPORTED;
+    hipLaunchKernelGGL(trace_product_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, RX, Y, RY, n, ld, out, vec,
+                       tp_chunk(tiles));
     return check_launch();
 }
 

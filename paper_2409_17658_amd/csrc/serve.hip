@@ -42,43 +42,44 @@ struct TPDesc {
     const u16 *Y;
     const int64_t *RY;
     int64_t n, ld, tiles, first_block;
-    int vec;
+    int vec, chunk;
 };
 
 constexpr int GT = TPI;  // square tiles of the trace routine
 
-// Grid-stride over the tiles of all queries of the batch (query q owns tiles
-// [first_block, first_block + tiles^2)); a block keeps a running minimum for
-// the query it is in and issues one atomic each time it leaves a query.
+// Blocks of one query of n x n operands (tp_chunk tiles each).
+static inline int64_t trace_blocks(int64_t n) { return tp_blocks((n + GT - 1) / GT); }
+
+// One launch for all queries of a batch: query q owns the blocks
+// [first_block, first_block + trace_blocks(n)); each block takes q.chunk
+// consecutive tiles of its query and folds their minimum into the query's
+// result word.
 __global__ __launch_bounds__(256) void grouped_trace_product_kernel(const TPDesc *__restrict__ d, int nq,
-                                                                    int64_t total, int64_t *out)
+                                                                    int64_t *out)
 {
     static_assert(TPI == TPL, "square tiles");
     __shared__ TPShared sh;
-    int cur = -1;
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nq - 1;  // last q with first_block <= b (every thread, same answer)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (d[mid].first_block <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const TPDesc q = d[lo];
+    const int64_t total = q.tiles * q.tiles;
+    const int64_t t0 = (b - q.first_block) * q.chunk, t1 = t0 + q.chunk < total ? t0 + q.chunk : total;
     int64_t best = ROW_NONE;
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        int lo = 0, hi = nq - 1;  // last q with first_block <= b (every thread, same answer)
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (d[mid].first_block <= b)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        if (lo != cur) {
-            if (threadIdx.x == 0 && cur >= 0 && best != ROW_NONE) atomicMin((long long *)&out[cur], (long long)best);
-            cur = lo;
-            best = ROW_NONE;
-        }
-        const TPDesc q = d[lo];
+    for (int64_t t = t0; t < t1; t++) {
         int64_t ti, tl;
-        tp_tile_of(b - q.first_block, q.tiles, ti, tl);
+        tp_tile_of(t, q.tiles, ti, tl);
         const int64_t v = tp_tile(q.X, q.RX, q.Y, q.RY, q.n, q.ld, ti * GT, tl * GT, q.vec != 0, sh);
         best = v < best ? v : best;
         __syncthreads();  // the next tile reuses sh
     }
-    if (threadIdx.x == 0 && cur >= 0 && best != ROW_NONE) atomicMin((long long *)&out[cur], (long long)best);
+    if (threadIdx.x == 0) tp_fold_min(&out[lo], best);
 }
 
 __global__ void fill_none_kernel(int64_t *p, int count)
@@ -389,6 +390,7 @@ static void worker_main(Server *Sp)
                 break;
             }
         std::vector<Request> batch;
+        int64_t batch_blocks = 0;  // grid of the grouped launch
         for (auto &kv : S.waiting) {
             Ladder &L = S.ladders[kv.first];
             if (L.state == Ladder::FAILED) {
@@ -407,9 +409,11 @@ static void worker_main(Server *Sp)
                     complete(S, r, L.baby_trace[j], MPR_OK, S.now());
                     continue;
                 }
-                if (!slot || (int)batch.size() >= S.opt.max_batch) break;
+                const int64_t qb = trace_blocks(L.n);
+                if (!slot || (int)batch.size() >= S.opt.max_batch || batch_blocks + qb > INT32_MAX) break;
                 dq.pop_front();
                 batch.push_back(r);
+                batch_blocks += qb;
             }
         }
         if (slot && !batch.empty()) {
@@ -420,8 +424,9 @@ static void worker_main(Server *Sp)
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
                 const int64_t tiles = (L.n + GT - 1) / GT;
                 const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
-                slot->desc_host[q] = TPDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, tiles, blocks, vec};
-                blocks += tiles * tiles;
+                slot->desc_host[q] =
+                    TPDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, tiles, blocks, vec, tp_chunk(tiles)};
+                blocks += trace_blocks(L.n);
                 L.inflight++;
                 L.last_use = S.now();
             }
@@ -430,9 +435,8 @@ static void worker_main(Server *Sp)
             bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TPDesc) * nq, hipMemcpyHostToDevice,
                                      s) == hipSuccess;
             hipLaunchKernelGGL(fill_none_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, slot->out_dev, nq);
-            const int64_t grid = std::min<int64_t>(blocks, (int64_t)device_cu_count() * TP_BLOCKS_PER_CU);
-            hipLaunchKernelGGL(grouped_trace_product_kernel, dim3((unsigned)grid), dim3(256), 0, s, slot->desc_dev,
-                               nq, blocks, slot->out_dev);
+            hipLaunchKernelGGL(grouped_trace_product_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
+                               nq, slot->out_dev);
             ok = ok && hipGetLastError() == hipSuccess;
             ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * nq, hipMemcpyDeviceToHost, s) == hipSuccess;
             ok = ok && hipEventRecord(slot->done, s) == hipSuccess;

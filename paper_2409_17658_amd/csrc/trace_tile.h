@@ -51,8 +51,21 @@ __device__ __forceinline__ uint4 tp_load8(const u16 *M, int64_t ld, int64_t n, i
 // blocks in flight read both X (rows i, along l) and Y (rows l, along i) in
 // runs of several KB per row instead of one 128-byte piece per row.
 constexpr int TP_G = 32;
-// Resident blocks per CU a grid-stride launch of the trace routine uses.
-constexpr int TP_BLOCKS_PER_CU = 8;
+// Tiles per block.  Launches give every block `chunk` consecutive tiles
+// (one grid of short-lived blocks, not a persistent grid-stride one: the
+// CU's arbiter favours older waves, so of resident blocks that split the
+// tiles statically the youngest finish last).  Large traces take 4 tiles a
+// block, which keeps the blocks (and their folds) few; below 8192 tiles (2048
+// blocks of 4, 8 per CU of 256) a trace is latency-bound and takes one tile
+// a block, so that all its tiles run at once.
+constexpr int TP_CHUNK = 4;
+constexpr int64_t TP_CHUNK_FROM = 8192;
+inline int tp_chunk(int64_t tiles) { return tiles * tiles >= TP_CHUNK_FROM ? TP_CHUNK : 1; }
+inline int64_t tp_blocks(int64_t tiles)
+{
+    const int c = tp_chunk(tiles);
+    return (tiles * tiles + c - 1) / c;
+}
 __device__ __forceinline__ void tp_tile_of(int64_t t, int64_t tiles, int64_t &ti, int64_t &tl)
 {
     const int64_t width = TP_G * tiles;
@@ -61,6 +74,18 @@ __device__ __forceinline__ void tp_tile_of(int64_t t, int64_t tiles, int64_t &ti
     const int64_t w = t % width;
     ti = first + w % gs;
     tl = w / gs;
+}
+
+// Folds a block's minimum into *out (thread 0).  The word only decreases,
+// so a block whose minimum is not below what a relaxed load of it sees
+// skips its atomic: with one atomic per block, tens of thousands of
+// same-address atomics would serialise, while few blocks improve on the
+// running minimum once the first ones have folded theirs.
+__device__ __forceinline__ void tp_fold_min(int64_t *out, int64_t best)
+{
+    if (best == ROW_NONE) return;
+    const int64_t seen = __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (best < seen) atomicMin((long long *)out, (long long)best);
 }
 
 // Block-wide (256 threads) minimum of the tile; the value is returned to

@@ -341,6 +341,35 @@ def test_trace_of_product_offsets_and_layouts(mpr):
     assert got == _trace_ref(X, base, Y, base)
 
 
+def test_trace_of_product_large_chunked(mpr):
+    """n = 5900: 93^2 = 8649 tiles, above the size from which the trace
+    launch gives each block several tiles (the last block holds one).  The
+    reference is the diagonal of (RX (+) X) (x) (RY (+) Y), entry by entry
+    from the definition (Corollary 7), then its minimum."""
+    n = 5900
+    X = synth.random_matrix(n, n, 41, 0, 2000, 0.25)
+    Y = synth.random_matrix(n, n, 42, 0, 2000, 0.25)
+    rx = (np.arange(n, dtype=np.int64) * 7919 % 61)
+    ry = (np.arange(n, dtype=np.int64) * 104729 % 53)
+    Xo, Yo = O.from_u16(X), O.from_u16(Y)
+    Xr = np.where(Xo == O.INF, O.INF, Xo + rx[:, None])
+    Yr = np.where(Yo == O.INF, O.INF, Yo + ry[:, None])
+    idx = np.arange(n, dtype=np.int64)
+    ref = int(O.minplus_at(Xr, Yr, idx, idx).min())
+    got = int(mpr.trace_of_product(_dev(mpr, X), torch.from_numpy(rx).cuda(), _dev(mpr, Y),
+                                   torch.from_numpy(ry).cuda()).item())
+    assert got == ref
+    # the minimum planted in the very last tile (the one-tile last block)
+    X2, Y2 = X.copy(), Y.copy()
+    X2[n - 1, n - 2] = 0
+    Y2[n - 2, n - 1] = 0
+    rx2, ry2 = rx + 100, ry + 100
+    rx2[n - 1], ry2[n - 2] = 0, 0
+    got2 = int(mpr.trace_of_product(_dev(mpr, X2), torch.from_numpy(rx2).cuda(), _dev(mpr, Y2),
+                                    torch.from_numpy(ry2).cuda()).item())
+    assert got2 == 0
+
+
 # ------------------------------------------------------------------ gamma_R and periods
 def test_config1_gamma_m3(mpr):
     """P_3 x C_n for n = 3..40 from one GPU chain, vs oracle and brute force."""

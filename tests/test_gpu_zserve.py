@@ -1,7 +1,9 @@
 """The query server: answers equal the oracle's gamma_R, and every answer is
 the same when the query runs alone and when it runs inside a Poisson mix
 (tolerance 0); a tiny HBM budget forces admission waits and evictions."""
+import json
 import math
+import os
 import time
 
 import pytest
@@ -20,6 +22,15 @@ def oracle_gamma(m, n):
         _CACHE[m] = O.find_period(A, 60)
     mu, lam, c, g = _CACHE[m]
     return O.gamma_from_period(n, mu, lam, c, g)
+
+
+def golden_gamma(m, n):
+    """Stored gamma_R table (written from the oracle by
+    tests/golden/make_roman_golden.py) extended by its period (Proposition 8)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "roman_m%d.json" % m)) as f:
+        d = json.load(f)
+    mu, lam, c = d["period"]
+    return O.gamma_from_period(n, mu, lam, c, {int(k): v for k, v in d["trace"].items()})
 
 
 @pytest.fixture(scope="module")
@@ -89,3 +100,25 @@ def test_query_keeps_other_results(serve):
         assert r["gamma"] == oracle_gamma(3, 18)
         held = S.poll(1000)
         assert [h["tag"] for h in held] == [4242] and held[0]["gamma"] == oracle_gamma(3, 17)
+
+
+def test_server_large_ladders_mixed_batches(serve):
+    """m = 7 (N = 2507, one tile per block of the grouped trace launch) and
+    m = 8 (N = 7411, several tiles per block) queries, alone and mixed in
+    the same launches, against the stored gamma_R tables."""
+    ns = [3, 31, 32, 33, 64, 65, 97, 150, 299, 300, 301, 517, 999, 1000]
+    qs = [(m, n) for n in ns for m in (7, 8)]
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=2, hbm_budget_bytes=32 << 30) as S:
+        alone = {q: S.query(*q)["gamma"] for q in qs}
+        for k, (m, n) in enumerate(qs):  # one burst: later queries wait for a slot and share launches
+            S.submit(m, n, k)
+        got, t_end = {}, time.monotonic() + 240
+        while len(got) < len(qs) and time.monotonic() < t_end:
+            for r in S.poll(20):
+                got[r["tag"]] = r
+        st = S.stats()
+    assert len(got) == len(qs)
+    for k, (m, n) in enumerate(qs):
+        assert got[k]["status"] == 0
+        assert got[k]["gamma"] == alone[(m, n)] == golden_gamma(m, n), (m, n)
+    assert st["max_batch_seen"] >= 2
