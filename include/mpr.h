@@ -275,8 +275,10 @@ mpr_status mpr_batch_workspace_size(const mpr_chain_desc *descs_host, int count,
 /* Plans a batch into the workspace: splits every chain into row panels
  * (row i of A^k depends only on row i of A^(k-1) and on A, so panels never
  * wait on each other), orders the panels longest first (a ragged last
- * panel costs as much as a full one) and uploads the work list.  Synchronous.  The workspace then holds the whole launch
- * state; mpr_batch_launch may be called (or captured) any number of times. */
+ * panel costs as much as a full one) and uploads the work list.
+ * Synchronous.  MPR_EUNSUPPORTED beyond 2^31 - 1 panels.  The workspace
+ * then holds the whole launch state; mpr_batch_launch may be called (or
+ * captured) any number of times. */
 mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count,
                           void *ws, size_t ws_bytes, mpr_stream stream);
 

@@ -443,6 +443,7 @@ extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count
                      [](const std::pair<double, BatchItem> &a, const std::pair<double, BatchItem> &b) {
                          return a.first > b.first;
                      });
+    if (items.size() > (size_t)INT32_MAX) return MPR_EUNSUPPORTED;  // one workgroup per panel
     std::vector<BatchItem> flat;
     for (auto &p : items) flat.push_back(p.second);
     hipStream_t s = as_stream(stream);
