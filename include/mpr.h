@@ -206,6 +206,20 @@ mpr_status mpr_trace_of_product(const uint16_t *X, const int64_t *RX,
                                 const uint16_t *Y, const int64_t *RY,
                                 int64_t n, int64_t ld, int64_t *d_gamma, mpr_stream stream);
 
+/* The same trace (Corollary 7) with the right operand given through the
+ * canonical form of its transpose: Y[l][i] = CY[i] + YT[i][l], so
+ * *d_gamma = min_i (RX[i] + CY[i] + min_l (X[i][l] + YT[i][l])) -- for
+ * YT, CY = the canonical form of (A^T)^j = (A^j)^T this is the trace of
+ * (RX (+) X) (x) A^j.  X and YT: device, n x n, row stride ld, any uint16
+ * (0xFFFF = infinity, sums exact in 32 bits); RX / CY: device, n int64
+ * each, MPR_ROW_NONE for an empty row, NULL for zero.  Both operands are
+ * read along rows once (a streaming pass, no transpose).  *d_gamma is
+ * MPR_ROW_NONE when every term has an infinite operand.  Asynchronous on
+ * stream. */
+mpr_status mpr_trace_of_product_t(const uint16_t *X, const int64_t *RX,
+                                  const uint16_t *YT, const int64_t *CY,
+                                  int64_t n, int64_t ld, int64_t *d_gamma, mpr_stream stream);
+
 /* ------------------------------------------------------------------ */
 /* Periodic regime (Lemma 2, Proposition 8, Algorithm 2).              */
 /* ------------------------------------------------------------------ */
@@ -349,9 +363,11 @@ typedef struct {
 
 /* Starts an engine with its own worker thread and two non-blocking HIP
  * streams (queries, ladder builds).  For each m it keeps the canonical
- * powers A^1..A^B and A^(B i), i <= (max_n - 1) / B, resident, and answers
- * n = B i + j (1 <= j <= B) as the trace of A^(B i) (x) A^j (Corollary 7)
- * without forming the product.  The engine allocates its ladders itself,
+ * powers A^(B i), i <= (max_n - 1) / B, and the canonical forms of
+ * (A^T)^j = (A^j)^T, j = 1..B, resident, and answers n = B i + j
+ * (1 <= j <= B) as the trace of A^(B i) (x) A^j (Corollary 7) without
+ * forming the product: one pass reading both matrices along rows (as
+ * mpr_trace_of_product_t).  The engine allocates its ladders itself,
  * within hbm_budget_bytes (least recently used idle ladders are evicted;
  * requests that do not fit wait).  *server_host receives an opaque handle. */
 mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host);

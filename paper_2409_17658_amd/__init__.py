@@ -90,6 +90,7 @@ _SIGS = {
     "mpr_minplus_power": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _SZ, _P, _P]),
     "mpr_trace_min": (_I, [_P, _I64, _I64, _P, _P, _P]),
     "mpr_trace_of_product": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
+    "mpr_trace_of_product_t": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
     "mpr_period_workspace_size": (_I, [_I64, _I64, _P]),
     "mpr_find_period": (_I, [_P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
     "mpr_period_workspace_size_ex": (_I, [_I64, _I64, _I, _P]),
@@ -346,6 +347,18 @@ def trace_of_product(X, RX, Y, RY, out=None, stream=None):
         out = torch.empty(1, dtype=torch.int64, device=X.device)
     _ok(lib().mpr_trace_of_product(_ptr(X), _vptr(RX, X.shape[0]), _ptr(Y), _vptr(RY, X.shape[0]), X.shape[0], _ld(X), _vptr(out, 1),
                                    _stream(stream)), "mpr_trace_of_product")
+    return out
+
+
+def trace_of_product_t(X, RX, YT, CY, out=None, stream=None):
+    """Trace of (RX (+) X) (x) Y with Y given through the canonical form
+    (YT, CY) of its transpose: Y[l][i] = CY[i] + YT[i][l]."""
+    if X.stride(0) != YT.stride(0):
+        raise ValueError("X and YT must share a leading dimension")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=X.device)
+    _ok(lib().mpr_trace_of_product_t(_ptr(X), _vptr(RX, X.shape[0]), _ptr(YT), _vptr(CY, X.shape[0]), X.shape[0],
+                                     _ld(X), _vptr(out, 1), _stream(stream)), "mpr_trace_of_product_t")
     return out
 
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "trace_rows.h"
 
 namespace mpr {
 
@@ -402,6 +403,16 @@ extern "C" mpr_status mpr_trace_of_product(const uint16_t *X, const int64_t *RX,
     mpr_status e = ensure_init();
     if (e != MPR_OK) return e;
     return trace_product_launch(X, RX, Y, RY, n, ld, d_gamma, as_stream(stream));
+}
+
+extern "C" mpr_status mpr_trace_of_product_t(const uint16_t *X, const int64_t *RX, const uint16_t *YT,
+                                             const int64_t *CY, int64_t n, int64_t ld, int64_t *d_gamma,
+                                             mpr_stream stream)
+{
+    if (n < 0 || !d_gamma || (n && (!X || !YT)) || !ld_ok(ld, n)) return MPR_EINVAL;
+    mpr_status e = ensure_init();
+    if (e != MPR_OK) return e;
+    return trace_product_t_launch(X, RX, YT, CY, n, ld, d_gamma, as_stream(stream));
 }
 
 extern "C" mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host)

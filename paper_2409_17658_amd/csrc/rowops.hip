@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "trace_rows.h"
 #include "trace_tile.h"
 
 namespace mpr {
@@ -355,6 +356,57 @@ mpr_status trace_product_launch(const u16 *X, const int64_t *RX, const u16 *Y, c
     if (grid > INT32_MAX) return MPR_EUNSUPPORTED;
     hipLaunchKernelGGL(trace_product_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, RX, Y, RY, n, ld, out, vec,
                        tp_chunk(tiles));
+    return check_launch();
+}
+
+// Trace of (RX (+) X) (x) Y with Y given as the canonical form (YT, CY) of
+// its transpose: TR_ROWS rows per block (trace_rows.h).
+__global__ __launch_bounds__(256) void trace_product_t_kernel(const u16 *X, const int64_t *RX, const u16 *YT,
+                                                              const int64_t *CY, int64_t n, int64_t ld,
+                                                              int64_t *out, int vec)
+{
+    tr_rows(X, RX, YT, CY, n, ld, (int64_t)blockIdx.x * TR_ROWS, vec != 0, out);
+}
+
+mpr_status trace_product_t_launch(const u16 *X, const int64_t *RX, const u16 *YT, const int64_t *CY, int64_t n,
+                                  int64_t ld, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_i64_kernel, dim3(1), dim3(64), 0, s, out, (int64_t)1, ROW_NONE);
+    mpr_status e = check_launch();
+    if (e != MPR_OK || n == 0) return e;
+    const int64_t grid = tr_blocks(n);
+    if (grid > INT32_MAX) return MPR_EUNSUPPORTED;
+    const int vec = aligned16(X) && aligned16(YT) && ld % 8 == 0;
+    hipLaunchKernelGGL(trace_product_t_kernel, dim3((unsigned)grid), dim3(256), 0, s, X, RX, YT, CY, n, ld, out, vec);
+    return check_launch();
+}
+
+// dst = src^T for an n x n matrix, 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_kernel(const u16 *src, int64_t lds, u16 *dst, int64_t ldd, int64_t n)
+{
+    __shared__ u16 t[64][66];
+    const int64_t tiles = (n + 63) / 64;
+    const int64_t i0 = ((int64_t)blockIdx.x / tiles) * 64, j0 = ((int64_t)blockIdx.x % tiles) * 64;
+    const int c = (int)(threadIdx.x & 63), r = (int)(threadIdx.x >> 6);
+#pragma unroll
+    for (int k = 0; k < 16; k++) {  // rows i0 + r + 4k of src, columns j0 + c
+        const int64_t i = i0 + r + 4 * k, j = j0 + c;
+        t[r + 4 * k][c] = (i < n && j < n) ? src[i * lds + j] : (u16)0xFFFF;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; k++) {  // rows j0 + r + 4k of dst, columns i0 + c
+        const int64_t j = j0 + r + 4 * k, i = i0 + c;
+        if (i < n && j < n) dst[j * ldd + i] = t[c][r + 4 * k];
+    }
+}
+
+mpr_status transpose_launch(const u16 *src, int64_t lds, u16 *dst, int64_t ldd, int64_t n, hipStream_t s)
+{
+    if (n == 0) return MPR_OK;
+    const int64_t tiles = (n + 63) / 64;
+    if (tiles * tiles > INT32_MAX) return MPR_EUNSUPPORTED;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(tiles * tiles)), dim3(256), 0, s, src, lds, dst, ldd, n);
     return check_launch();
 }
 

@@ -28,37 +28,36 @@
 #include <vector>
 
 #include "common.h"
-#include "trace_tile.h"
+#include "trace_rows.h"
 
 namespace mpr {
 
 mpr_status transfer_launch(int m, u16 *A, int64_t lda, hipStream_t s);
+mpr_status transpose_launch(const u16 *src, int64_t lds, u16 *dst, int64_t ldd, int64_t n, hipStream_t s);
 int64_t transfer_size(int m);
 
 // ------------------------------------------------------------ grouped trace-of-product
-struct TPDesc {
-    const u16 *X;
+// A query n = B i + j is the trace of A^(B i) (x) A^j (Corollary 7).  The
+// giant powers A^(B i) are kept in canonical form (rows), the baby powers as
+// the canonical forms of (A^T)^j = (A^j)^T, so one query is a row-streaming
+// pass over two matrices (trace_rows.h).
+struct TRDesc {
+    const u16 *X;     // A^(B i), canonical rows
     const int64_t *RX;
-    const u16 *Y;
-    const int64_t *RY;
-    int64_t n, ld, tiles, first_block;
-    int vec, chunk;
+    const u16 *YT;    // (A^T)^j, canonical rows
+    const int64_t *CY;
+    int64_t n, ld, first_block;
+    int vec;
 };
 
-constexpr int GT = TPI;  // square tiles of the trace routine
-
-// Blocks of one query of n x n operands (tp_chunk tiles each).
-static inline int64_t trace_blocks(int64_t n) { return tp_blocks((n + GT - 1) / GT); }
+// Blocks of one query of n x n operands.
+static inline int64_t trace_blocks(int64_t n) { return tr_blocks(n); }
 
 // One launch for all queries of a batch: query q owns the blocks
-// [first_block, first_block + trace_blocks(n)); each block takes q.chunk
-// consecutive tiles of its query and folds their minimum into the query's
-// result word.
-__global__ __launch_bounds__(256) void grouped_trace_product_kernel(const TPDesc *__restrict__ d, int nq,
-                                                                    int64_t *out)
+// [first_block, first_block + trace_blocks(n)); each block takes TR_ROWS
+// rows of its query and folds their minimum into the query's result word.
+__global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *__restrict__ d, int nq, int64_t *out)
 {
-    static_assert(TPI == TPL, "square tiles");
-    __shared__ TPShared sh;
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nq - 1;  // last q with first_block <= b (every thread, same answer)
     while (lo < hi) {
@@ -68,18 +67,8 @@ __global__ __launch_bounds__(256) void grouped_trace_product_kernel(const TPDesc
         else
             hi = mid - 1;
     }
-    const TPDesc q = d[lo];
-    const int64_t total = q.tiles * q.tiles;
-    const int64_t t0 = (b - q.first_block) * q.chunk, t1 = t0 + q.chunk < total ? t0 + q.chunk : total;
-    int64_t best = ROW_NONE;
-    for (int64_t t = t0; t < t1; t++) {
-        int64_t ti, tl;
-        tp_tile_of(t, q.tiles, ti, tl);
-        const int64_t v = tp_tile(q.X, q.RX, q.Y, q.RY, q.n, q.ld, ti * GT, tl * GT, q.vec != 0, sh);
-        best = v < best ? v : best;
-        __syncthreads();  // the next tile reuses sh
-    }
-    if (threadIdx.x == 0) tp_fold_min(&out[lo], best);
+    const TRDesc q = d[lo];
+    tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, (b - q.first_block) * TR_ROWS, q.vec != 0, &out[lo]);
 }
 
 __global__ void fill_none_kernel(int64_t *p, int count)
@@ -98,7 +87,7 @@ struct Ladder {
     int fail_status = MPR_OK;  // why a FAILED ladder failed
     void *mem = nullptr;
     size_t bytes = 0;
-    std::vector<u16 *> Nb, Ng;        // baby[1..B], giant[1..G] (giant[1] = baby[B])
+    std::vector<u16 *> Nb, Ng;        // baby[1..B] = (A^T)^j, giant[1..G] = A^(B i), canonical forms
     std::vector<int64_t *> Rb, Rg;
     std::vector<int64_t> baby_trace;  // host, index j = 1..B
     hipEvent_t ready = nullptr;
@@ -120,8 +109,8 @@ struct Request {
 struct Slot {
     bool busy = false;
     hipEvent_t done = nullptr;
-    TPDesc *desc_host = nullptr;  // pinned
-    TPDesc *desc_dev = nullptr;
+    TRDesc *desc_host = nullptr;  // pinned
+    TRDesc *desc_dev = nullptr;
     int64_t *out_dev = nullptr;
     int64_t *out_host = nullptr;  // pinned
     std::vector<Request> reqs;
@@ -163,9 +152,9 @@ static size_t ladder_bytes(int m, int B, int G, int64_t *n_out, int64_t *ld_out)
 {
     const int64_t n = transfer_size(m), ld = round_up(n, 8);
     const size_t mat = (size_t)round_up(n * ld * 2, 256), vec = (size_t)round_up(n * 8, 256);
-    // A, B babies, G-1 further giants, one folded operand; the scalars; the
-    // compressed-K plan of A used by the baby chain
-    const size_t count = 1 + (size_t)B + (size_t)(G > 1 ? G - 1 : 0) + 1;
+    // A, B babies, G giants, one folded operand; the scalars; the
+    // compressed-K plan (of A for the first giant, then of A^T for the babies)
+    const size_t count = 1 + (size_t)B + (size_t)G + 1;
     if (n_out) *n_out = n;
     if (ld_out) *ld_out = ld;
     return count * (mat + vec) + (size_t)round_up((int64_t)(B + 8) * 8, 256) + sparse_plan_bytes(n);
@@ -194,16 +183,12 @@ static mpr_status start_build(Server &S, Ladder &L)
     }
     L.Ng.assign(G + 1, nullptr);
     L.Rg.assign(G + 1, nullptr);
-    if (G >= 1) {
-        L.Ng[1] = L.Nb[B];
-        L.Rg[1] = L.Rb[B];
-    }
-    for (int i = 2; i <= G; i++) {
+    for (int i = 1; i <= G; i++) {
         L.Ng[i] = take_mat();
         L.Rg[i] = take_vec();
     }
     u16 *Bp = take_mat();
-    (void)take_vec();
+    int64_t *Rp = take_vec();
     int64_t *scal = (int64_t *)p;  // [0] s of the fold, [1..B] traces, then the status word
     p += round_up((int64_t)(B + 8) * 8, 256);
     void *plan = p;
@@ -212,10 +197,28 @@ static mpr_status start_build(Server &S, Ladder &L)
     hipStream_t s = S.bstream;
     mpr_status e = fill_i32_launch(L.status_dev, 1, 0, s);
     if (e == MPR_OK) e = transfer_launch(L.m, A, ld, s);
-    if (e == MPR_OK) e = copy_launch(A, ld, L.Nb[1], ld, n, n, s);
+    // The first giant A^B by the compressed-K chain on A (A stays sparse;
+    // identical results), alternating between Ng[1] and Bp so that step B
+    // lands in Ng[1].
+    if (G >= 1) {
+        u16 *buf[2] = {L.Ng[1], Bp};
+        int64_t *R[2] = {L.Rg[1], Rp};
+        int b = (B - 1) & 1;
+        if (e == MPR_OK) e = copy_launch(A, ld, buf[b], ld, n, n, s);
+        if (e == MPR_OK) e = normalise_launch(n, n, buf[b], ld, nullptr, nullptr, R[b], L.status_dev, nullptr, s);
+        if (e == MPR_OK && B >= 2) e = sparse_plan_launch(A, n, ld, plan, s);
+        for (int k = 2; k <= B && e == MPR_OK; k++) {
+            e = sparse_step_launch(buf[b], ld, n, plan, buf[b ^ 1], ld, s);
+            if (e == MPR_OK)
+                e = normalise_launch(n, n, buf[b ^ 1], ld, R[b], nullptr, R[b ^ 1], L.status_dev, nullptr, s);
+            b ^= 1;
+        }
+    }
+    // Baby steps: the canonical forms of (A^T)^j = (A^j)^T by the same chain
+    // on A^T (plan built from the raw A^T before it is normalised in place).
+    if (e == MPR_OK) e = transpose_launch(A, ld, L.Nb[1], ld, n, s);
+    if (e == MPR_OK && B >= 2) e = sparse_plan_launch(L.Nb[1], n, ld, plan, s);
     if (e == MPR_OK) e = normalise_launch(n, n, L.Nb[1], ld, nullptr, nullptr, L.Rb[1], L.status_dev, nullptr, s);
-    // baby steps by the compressed-K chain (A stays sparse; identical results)
-    if (e == MPR_OK && B >= 2) e = sparse_plan_launch(A, n, ld, plan, s);
     for (int j = 2; j <= B && e == MPR_OK; j++) {
         e = sparse_step_launch(L.Nb[j - 1], ld, n, plan, L.Nb[j], ld, s);
         if (e == MPR_OK)
@@ -422,20 +425,18 @@ static void worker_main(Server *Sp)
                 const Request &r = batch[q];
                 Ladder &L = S.ladders[r.m];
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
-                const int64_t tiles = (L.n + GT - 1) / GT;
                 const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
-                slot->desc_host[q] =
-                    TPDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, tiles, blocks, vec, tp_chunk(tiles)};
+                slot->desc_host[q] = TRDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, blocks, vec};
                 blocks += trace_blocks(L.n);
                 L.inflight++;
                 L.last_use = S.now();
             }
             const int nq = (int)batch.size();
             hipStream_t s = S.qstream;
-            bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TPDesc) * nq, hipMemcpyHostToDevice,
+            bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TRDesc) * nq, hipMemcpyHostToDevice,
                                      s) == hipSuccess;
             hipLaunchKernelGGL(fill_none_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, slot->out_dev, nq);
-            hipLaunchKernelGGL(grouped_trace_product_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
+            hipLaunchKernelGGL(grouped_trace_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
                                nq, slot->out_dev);
             ok = ok && hipGetLastError() == hipSuccess;
             ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * nq, hipMemcpyDeviceToHost, s) == hipSuccess;
@@ -482,9 +483,9 @@ extern "C" mpr_status mpr_server_create(const mpr_server_options *opt, void **se
     S->slots.resize(opt->slots);
     for (auto &sl : S->slots) {
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&sl.desc_host, sizeof(TPDesc) * opt->max_batch) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&sl.desc_host, sizeof(TRDesc) * opt->max_batch) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&sl.out_host, 8 * opt->max_batch) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.desc_dev, sizeof(TPDesc) * opt->max_batch) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.desc_dev, sizeof(TRDesc) * opt->max_batch) == hipSuccess;
         ok = ok && hipMalloc((void **)&sl.out_dev, 8 * opt->max_batch) == hipSuccess;
     }
     if (!ok) {

@@ -370,6 +370,68 @@ def test_trace_of_product_large_chunked(mpr):
     assert got2 == 0
 
 
+def _trace_t_ref(X, rx, YT, cy):
+    """min of the diagonal of (RX (+) X) (x) Y with Y[l][i] = CY[i] + YT[i][l],
+    every diagonal entry from the definition of the product (Corollary 7)."""
+    Xo, Yo = O.from_u16(X), O.from_u16(YT)
+    Xr = np.where((Xo == O.INF) | (rx[:, None] == O.INF), O.INF, Xo + np.where(rx == O.INF, 0, rx)[:, None])
+    Yr = np.where((Yo == O.INF) | (cy[:, None] == O.INF), O.INF, Yo + np.where(cy == O.INF, 0, cy)[:, None])
+    idx = np.arange(X.shape[0], dtype=np.int64)
+    return int(O.minplus_at(Xr, np.ascontiguousarray(Yr.T), idx, idx).min())
+
+
+@pytest.mark.parametrize("n", [1, 7, 203, 520, 1100])
+def test_trace_of_product_t(mpr, n):
+    """Right operand given through the canonical form of its transpose:
+    row lengths below one 8-value chunk, ragged tails, one and two chunks
+    per lane; empty rows on either side, an all-infinite row."""
+    X = synth.random_matrix(n, n, 51, 0, 900, 0.4)
+    YT = synth.random_matrix(n, n, 52, 0, 900, 0.4)
+    rx = (np.arange(n, dtype=np.int64) * 13 % 17)
+    cy = (np.arange(n, dtype=np.int64) * 7 % 19)
+    if n > 8:
+        rx[3] = O.INF
+        cy[5] = O.INF
+        X[6, :] = 0xFFFF
+    ref = _trace_t_ref(X, rx, YT, cy)
+    got = int(mpr.trace_of_product_t(_dev(mpr, X), torch.from_numpy(rx).cuda(), _dev(mpr, YT),
+                                     torch.from_numpy(cy).cuda()).item())
+    assert got == ref
+
+
+def test_trace_of_product_t_offsets_and_layouts(mpr):
+    """Huge offsets, NULL offsets, an all-infinite operand, a row stride that
+    is not a multiple of 8 (element-wise loads), and n = 5900 (large)."""
+    n = 300
+    X = synth.random_matrix(n, n, 53, 0, 40, 0.3)
+    YT = synth.random_matrix(n, n, 54, 0, 40, 0.3)
+    base = np.arange(n, dtype=np.int64) % 9
+    got = int(mpr.trace_of_product_t(_dev(mpr, X), torch.from_numpy(base + (1 << 50)).cuda(), _dev(mpr, YT),
+                                     torch.from_numpy(base + 123456789012).cuda()).item())
+    assert got == _trace_t_ref(X, base + (1 << 50), YT, base + 123456789012)
+    zero = np.zeros(n, dtype=np.int64)
+    got = int(mpr.trace_of_product_t(_dev(mpr, X), None, _dev(mpr, YT), None).item())
+    assert got == _trace_t_ref(X, zero, YT, zero)
+    inf = np.full((n, n), 0xFFFF, np.uint16)
+    got = int(mpr.trace_of_product_t(_dev(mpr, inf), None, _dev(mpr, YT), None).item())
+    assert got == O.INF
+    Xp = np.full((n, n + 3), 0xFFFF, np.uint16)
+    Yp = np.full((n, n + 3), 0xFFFF, np.uint16)
+    Xp[:, :n], Yp[:, :n] = X, YT
+    Xd, Yd = torch.from_numpy(Xp).cuda()[:, :n], torch.from_numpy(Yp).cuda()[:, :n]
+    assert Xd.stride(0) % 8
+    got = int(mpr.trace_of_product_t(Xd, torch.from_numpy(base).cuda(), Yd, torch.from_numpy(base).cuda()).item())
+    assert got == _trace_t_ref(X, base, YT, base)
+    n = 5900
+    X = synth.random_matrix(n, n, 55, 0, 2000, 0.25)
+    YT = synth.random_matrix(n, n, 56, 0, 2000, 0.25)
+    rx = (np.arange(n, dtype=np.int64) * 7919 % 61)
+    cy = (np.arange(n, dtype=np.int64) * 104729 % 53)
+    got = int(mpr.trace_of_product_t(_dev(mpr, X), torch.from_numpy(rx).cuda(), _dev(mpr, YT),
+                                     torch.from_numpy(cy).cuda()).item())
+    assert got == _trace_t_ref(X, rx, YT, cy)
+
+
 # ------------------------------------------------------------------ gamma_R and periods
 def test_config1_gamma_m3(mpr):
     """P_3 x C_n for n = 3..40 from one GPU chain, vs oracle and brute force."""

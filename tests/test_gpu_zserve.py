@@ -90,6 +90,17 @@ def test_server_ladder_boundaries(serve):
                 assert r["status"] == 0 and r["gamma"] == oracle_gamma(m, n), (m, n, r)
 
 
+@pytest.mark.parametrize("B,max_n", [(1, 12), (5, 23), (16, 16)])
+def test_server_ladder_shapes(serve, B, max_n):
+    """B = 1 (the first giant is A itself), an odd B (the chain to A^B starts
+    on the other buffer), and max_n <= B (no giant at all): every n."""
+    with serve.Server(baby=B, max_n=max_n, max_batch=16, slots=2, hbm_budget_bytes=1 << 30) as S:
+        for m in (2, 3, 5):
+            for n in range(3, max_n + 1):
+                r = S.query(m, n)
+                assert r["status"] == 0 and r["gamma"] == oracle_gamma(m, n), (m, n, r)
+
+
 def test_query_keeps_other_results(serve):
     """A result that arrives while query() waits for its own is handed to
     the next poll(), not dropped."""
