@@ -344,6 +344,10 @@ typedef struct {
     int max_batch;            /* most queries in one grouped launch */
     int slots;                /* grouped launches in flight (1..64) */
     size_t hbm_budget_bytes;  /* ladders are admitted only within this */
+    int wide_only;            /* 0: keep byte copies of the ladder powers and
+                                 answer from them when every finite entry is
+                                 <= 127 (half the bytes per query; exact);
+                                 1: uint16 only */
 } mpr_server_options;
 
 typedef struct {
@@ -359,6 +363,7 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, batches, max_batch_seen;
     int64_t builds, evictions, admission_waits, resident_bytes;
+    int64_t narrow_builds;    /* finished builds whose queries read byte copies */
 } mpr_server_stats;
 
 /* Starts an engine with its own worker thread and two non-blocking HIP
@@ -367,7 +372,8 @@ typedef struct {
  * (A^T)^j = (A^j)^T, j = 1..B, resident, and answers n = B i + j
  * (1 <= j <= B) as the trace of A^(B i) (x) A^j (Corollary 7) without
  * forming the product: one pass reading both matrices along rows (as
- * mpr_trace_of_product_t).  The engine allocates its ladders itself,
+ * mpr_trace_of_product_t), over byte copies of them unless wide_only is set
+ * or an entry does not fit (canonical Roman powers have entries <= 2m).  The engine allocates its ladders itself,
  * within hbm_budget_bytes (least recently used idle ladders are evicted;
  * requests that do not fit wait).  *server_host receives an opaque handle. */
 mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host);
@@ -384,8 +390,9 @@ mpr_status mpr_server_poll(void *server, mpr_query_result *out_host, int capacit
 mpr_status mpr_server_stats_get(void *server, mpr_server_stats *out_host);
 /* Seconds since the engine started, on the clock of the result times. */
 double mpr_server_now(void *server);
-/* Device bytes one ladder of m takes for the given baby step and max_n. */
-int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n);
+/* Device bytes one ladder of m takes for the given baby step, max_n and
+ * wide_only option. */
+int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n, int wide_only);
 /* Stops the worker, waits for outstanding GPU work, frees everything. */
 mpr_status mpr_server_destroy(void *server);
 

@@ -46,8 +46,9 @@ struct TRDesc {
     const int64_t *RX;
     const u16 *YT;    // (A^T)^j, canonical rows
     const int64_t *CY;
-    int64_t n, ld, first_block;
-    int vec;
+    const uint8_t *X8, *YT8;  // their byte copies, used when `narrow`
+    int64_t n, ld, ld8, first_block;
+    int vec, narrow;
 };
 
 // Blocks of one query of n x n operands.
@@ -68,7 +69,49 @@ __global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *_
             hi = mid - 1;
     }
     const TRDesc q = d[lo];
-    tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, (b - q.first_block) * TR_ROWS, q.vec != 0, &out[lo]);
+    if (q.narrow)  // block-uniform
+        tr8_rows(q.X8, q.RX, q.YT8, q.CY, q.n, q.ld8, (b - q.first_block) * TR_ROWS, true, &out[lo]);
+    else
+        tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, (b - q.first_block) * TR_ROWS, q.vec != 0, &out[lo]);
+}
+
+// Byte copy of an n x n canonical power (0xFFFF -> 0xFF), one row per
+// block; *wide is set when a finite entry exceeds TR8_FMAX (the copy is then
+// not used).  Entries of canonical Roman powers stay below 2m + 1.
+__global__ __launch_bounds__(256) void pack8_kernel(const u16 *src, int64_t ld, uint8_t *dst, int64_t ld8, int64_t n,
+                                                    int vec, int32_t *wide)
+{
+    const int64_t i = blockIdx.x;
+    const gu16 *s = glob(src) + i * ld;
+    uint8_t *d = dst + i * ld8;
+    bool w = false;
+    for (int64_t j = (int64_t)threadIdx.x * 8; j < n; j += 256 * 8) {
+        const bool full = vec && j + 8 <= n;
+        uint32_t v[8];
+        if (full) {
+            const uint4 q = gload16(s + j);
+            const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = (qw[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = j + e < n ? (uint32_t)s[j + e] : 0xFFFFu;
+        }
+        uint32_t b[2] = {0, 0};
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            w |= v[e] != 0xFFFFu && v[e] > TR8_FMAX;
+            b[e >> 2] |= (v[e] == 0xFFFFu ? 0xFFu : (v[e] & 0xFFu)) << ((e & 3) * 8);
+        }
+        if (full) {
+            *(uint2 *)(d + j) = make_uint2(b[0], b[1]);  // 8-byte aligned: ld8 % 16 == 0
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++)
+                if (j + e < n) d[j + e] = (uint8_t)(b[e >> 2] >> ((e & 3) * 8));
+        }
+    }
+    if (w) atomicOr(wide, 1);
 }
 
 __global__ void fill_none_kernel(int64_t *p, int count)
@@ -89,6 +132,10 @@ struct Ladder {
     size_t bytes = 0;
     std::vector<u16 *> Nb, Ng;        // baby[1..B] = (A^T)^j, giant[1..G] = A^(B i), canonical forms
     std::vector<int64_t *> Rb, Rg;
+    std::vector<uint8_t *> Nb8, Ng8;  // byte copies (row stride ld8), when the server keeps them
+    int64_t ld8 = 0;
+    int32_t *wide_dev = nullptr;      // set by the pack pass when an entry does not fit a byte
+    bool narrow = false;              // queries read the byte copies
     std::vector<int64_t> baby_trace;  // host, index j = 1..B
     hipEvent_t ready = nullptr;
     int64_t *trace_dev = nullptr;
@@ -148,16 +195,19 @@ static void stats_update(Server &S, F f)
     f(S.stats);
 }
 
-static size_t ladder_bytes(int m, int B, int G, int64_t *n_out, int64_t *ld_out)
+static size_t ladder_bytes(int m, int B, int G, bool bytes8, int64_t *n_out, int64_t *ld_out)
 {
     const int64_t n = transfer_size(m), ld = round_up(n, 8);
     const size_t mat = (size_t)round_up(n * ld * 2, 256), vec = (size_t)round_up(n * 8, 256);
     // A, B babies, G giants, one folded operand; the scalars; the
-    // compressed-K plan (of A for the first giant, then of A^T for the babies)
+    // compressed-K plan (of A for the first giant, then of A^T for the
+    // babies); the byte copies of the babies and giants
     const size_t count = 1 + (size_t)B + (size_t)G + 1;
+    const size_t mat8 = bytes8 ? (size_t)round_up(n * round_up(n, 16), 256) : 0;
     if (n_out) *n_out = n;
     if (ld_out) *ld_out = ld;
-    return count * (mat + vec) + (size_t)round_up((int64_t)(B + 8) * 8, 256) + sparse_plan_bytes(n);
+    return count * (mat + vec) + (size_t)round_up((int64_t)(B + 8) * 8, 256) + sparse_plan_bytes(n) +
+           (size_t)(B + G) * mat8;
 }
 
 static int giant_count(const mpr_server_options &o) { return (int)((o.max_n - 1) / o.baby); }
@@ -166,7 +216,8 @@ static int giant_count(const mpr_server_options &o) { return (int)((o.max_n - 1)
 static mpr_status start_build(Server &S, Ladder &L)
 {
     const int B = S.opt.baby, G = giant_count(S.opt);
-    L.bytes = ladder_bytes(L.m, B, G, &L.n, &L.ld);
+    const bool bytes8 = !S.opt.wide_only;
+    L.bytes = ladder_bytes(L.m, B, G, bytes8, &L.n, &L.ld);
     if (hipMalloc(&L.mem, L.bytes) != hipSuccess) return MPR_ENOMEM;
     const int64_t n = L.n, ld = L.ld;
     const size_t mat = (size_t)round_up(n * ld * 2, 256), vec = (size_t)round_up(n * 8, 256);
@@ -189,13 +240,24 @@ static mpr_status start_build(Server &S, Ladder &L)
     }
     u16 *Bp = take_mat();
     int64_t *Rp = take_vec();
-    int64_t *scal = (int64_t *)p;  // [0] s of the fold, [1..B] traces, then the status word
+    int64_t *scal = (int64_t *)p;  // [0] s of the fold, [1..B] traces, the status word, the byte-copy flag
     p += round_up((int64_t)(B + 8) * 8, 256);
     void *plan = p;
+    p += sparse_plan_bytes(n);
     L.trace_dev = scal + 1;
     L.status_dev = (int32_t *)(scal + 2 + B);
+    L.wide_dev = (int32_t *)(scal + 3 + B);
+    L.ld8 = round_up(n, 16);
+    const size_t mat8 = (size_t)round_up(n * L.ld8, 256);
+    L.Nb8.assign(B + 1, nullptr);
+    L.Ng8.assign(G + 1, nullptr);
+    if (bytes8) {
+        for (int j = 1; j <= B; j++, p += mat8) L.Nb8[j] = (uint8_t *)p;
+        for (int i = 1; i <= G; i++, p += mat8) L.Ng8[i] = (uint8_t *)p;
+    }
     hipStream_t s = S.bstream;
     mpr_status e = fill_i32_launch(L.status_dev, 1, 0, s);
+    if (e == MPR_OK) e = fill_i32_launch(L.wide_dev, 1, 0, s);
     if (e == MPR_OK) e = transfer_launch(L.m, A, ld, s);
     // The first giant A^B by the compressed-K chain on A (A stays sparse;
     // identical results), alternating between Ng[1] and Bp so that step B
@@ -230,6 +292,17 @@ static mpr_status start_build(Server &S, Ladder &L)
         e = gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, Bp, ld, L.Ng[i], ld, s);
         if (e == MPR_OK)
             e = normalise_launch(n, n, L.Ng[i], ld, L.Rg[i - 1], scal, L.Rg[i], L.status_dev, nullptr, s);
+    }
+    // byte copies for the query pass (half the bytes per query)
+    if (bytes8 && n > 0 && e == MPR_OK) {
+        const int vec8 = ld % 8 == 0;  // ladder buffers are 256-byte aligned
+        for (int k = 1; k <= B + G && e == MPR_OK; k++) {
+            const u16 *src = k <= B ? L.Nb[k] : L.Ng[k - B];
+            uint8_t *dst = k <= B ? L.Nb8[k] : L.Ng8[k - B];
+            hipLaunchKernelGGL(pack8_kernel, dim3((unsigned)n), dim3(256), 0, s, src, ld, dst, L.ld8, n, vec8,
+                               L.wide_dev);
+            e = check_launch();
+        }
     }
     if (e != MPR_OK) return e;
     if (hipEventCreateWithFlags(&L.ready, hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
@@ -271,7 +344,7 @@ static void complete(Server &S, const Request &r, int64_t gamma, int status, dou
 static bool admit(Server &S, int m)
 {
     const int B = S.opt.baby, G = giant_count(S.opt);
-    const size_t need = ladder_bytes(m, B, G, nullptr, nullptr);
+    const size_t need = ladder_bytes(m, B, G, !S.opt.wide_only, nullptr, nullptr);
     if (need > S.opt.hbm_budget_bytes) return false;
     while (S.resident + need > S.opt.hbm_budget_bytes) {
         Ladder *victim = nullptr;
@@ -338,11 +411,14 @@ static void worker_main(Server *Sp)
         for (auto &kv : S.ladders) {
             Ladder &L = kv.second;
             if (L.state != Ladder::BUILDING || hipEventQuery(L.ready) != hipSuccess) continue;
-            int32_t st = 0;
+            int32_t st = 0, wide = 1;
             L.baby_trace.assign(B + 1, ROW_NONE);
             if (hipMemcpy(&st, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&wide, L.wide_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) != hipSuccess)
                 st = MPR_EHIP;
+            L.narrow = !S.opt.wide_only && wide == 0;
+            if (st == 0 && L.narrow) stats_update(S, [](mpr_server_stats &t) { t.narrow_builds++; });
             L.build_s = S.now() - L.build_s0;
             L.last_use = S.now();
             if (st == 0) {
@@ -360,7 +436,7 @@ static void worker_main(Server *Sp)
                 complete(S, r, ROW_NONE, MPR_EINVAL, S.now());
                 continue;
             }
-            if (ladder_bytes(r.m, B, giant_count(S.opt), nullptr, nullptr) > S.opt.hbm_budget_bytes) {
+            if (ladder_bytes(r.m, B, giant_count(S.opt), !S.opt.wide_only, nullptr, nullptr) > S.opt.hbm_budget_bytes) {
                 complete(S, r, ROW_NONE, MPR_ENOMEM, S.now());  // could never be admitted
                 continue;
             }
@@ -426,7 +502,8 @@ static void worker_main(Server *Sp)
                 Ladder &L = S.ladders[r.m];
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
                 const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
-                slot->desc_host[q] = TRDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.n, L.ld, blocks, vec};
+                slot->desc_host[q] = TRDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.Ng8[i], L.Nb8[j],
+                                            L.n,     L.ld,     L.ld8,    blocks,   vec,      L.narrow ? 1 : 0};
                 blocks += trace_blocks(L.n);
                 L.inflight++;
                 L.last_use = S.now();
@@ -546,10 +623,10 @@ extern "C" double mpr_server_now(void *server)
     return S ? S->now() : 0.0;
 }
 
-extern "C" int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n)
+extern "C" int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n, int wide_only)
 {
     if (m < 1 || m > 11 || baby < 1 || max_n < 3) return -1;
-    return (int64_t)ladder_bytes(m, baby, (int)((max_n - 1) / baby), nullptr, nullptr);
+    return (int64_t)ladder_bytes(m, baby, (int)((max_n - 1) / baby), wide_only == 0, nullptr, nullptr);
 }
 
 extern "C" mpr_status mpr_server_destroy(void *server)

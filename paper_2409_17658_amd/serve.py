@@ -15,8 +15,8 @@ from . import MprError, QueryResult, ServerOptions, ServerStats, lib
 
 class Server:
     def __init__(self, device: int = 0, baby: int = 32, max_n: int = 1000, max_batch: int = 256,
-                 slots: int = 4, hbm_budget_bytes: int = 200 << 30):
-        self.opt = ServerOptions(device, baby, max_n, max_batch, slots, hbm_budget_bytes)
+                 slots: int = 4, hbm_budget_bytes: int = 200 << 30, wide_only: bool = False):
+        self.opt = ServerOptions(device, baby, max_n, max_batch, slots, hbm_budget_bytes, int(bool(wide_only)))
         h = ctypes.c_void_p()
         st = lib().mpr_server_create(ctypes.byref(self.opt), ctypes.byref(h))
         if st != 0:
@@ -81,8 +81,8 @@ class Server:
         self.close()
 
 
-def ladder_bytes(m: int, baby: int = 32, max_n: int = 1000) -> int:
-    return int(lib().mpr_server_ladder_bytes(m, baby, max_n))
+def ladder_bytes(m: int, baby: int = 32, max_n: int = 1000, wide_only: bool = False) -> int:
+    return int(lib().mpr_server_ladder_bytes(m, baby, max_n, int(bool(wide_only))))
 
 
 def run_open_loop(server: Server, arrivals, timeout_s: float = 600.0):

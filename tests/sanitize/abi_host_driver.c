@@ -39,7 +39,8 @@ int main(void)
     CHECK(mpr_period_workspace_size_ex(100, 4, 8, &bytes) == MPR_EINVAL);
     for (int s = 0; s < 8; s++) CHECK(mpr_status_string(s) != NULL);
     CHECK(mpr_gemm_config_count() > 0 && mpr_batch_config_count() > 0);
-    CHECK(mpr_server_ladder_bytes(9, 32, 1000) > 0 && mpr_server_ladder_bytes(0, 32, 1000) < 0);
+    CHECK(mpr_server_ladder_bytes(9, 32, 1000, 0) > mpr_server_ladder_bytes(9, 32, 1000, 1));
+    CHECK(mpr_server_ladder_bytes(9, 32, 1000, 1) > 0 && mpr_server_ladder_bytes(0, 32, 1000, 0) < 0);
     printf("abi host sanitizer run ok\n");
     return 0;
 }

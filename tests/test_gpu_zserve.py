@@ -113,13 +113,15 @@ def test_query_keeps_other_results(serve):
         assert [h["tag"] for h in held] == [4242] and held[0]["gamma"] == oracle_gamma(3, 17)
 
 
-def test_server_large_ladders_mixed_batches(serve):
-    """m = 7 (N = 2507, one tile per block of the grouped trace launch) and
-    m = 8 (N = 7411, several tiles per block) queries, alone and mixed in
-    the same launches, against the stored gamma_R tables."""
+@pytest.mark.parametrize("wide_only", [False, True])
+def test_server_large_ladders_mixed_batches(serve, wide_only):
+    """m = 7 (N = 2507) and m = 8 (N = 7411) queries, alone and mixed in the
+    same launches, from the byte copies of the ladders and from the uint16
+    powers, against the stored gamma_R tables."""
     ns = [3, 31, 32, 33, 64, 65, 97, 150, 299, 300, 301, 517, 999, 1000]
     qs = [(m, n) for n in ns for m in (7, 8)]
-    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=2, hbm_budget_bytes=32 << 30) as S:
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=2, hbm_budget_bytes=32 << 30,
+                      wide_only=wide_only) as S:
         alone = {q: S.query(*q)["gamma"] for q in qs}
         for k, (m, n) in enumerate(qs):  # one burst: later queries wait for a slot and share launches
             S.submit(m, n, k)
@@ -133,3 +135,4 @@ def test_server_large_ladders_mixed_batches(serve):
         assert got[k]["status"] == 0
         assert got[k]["gamma"] == alone[(m, n)] == golden_gamma(m, n), (m, n)
     assert st["max_batch_seen"] >= 2
+    assert st["narrow_builds"] == (0 if wide_only else 2)
