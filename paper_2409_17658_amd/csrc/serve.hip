@@ -385,10 +385,14 @@ static void worker_main(Server *Sp)
         std::vector<Request> fresh;
         {
             std::unique_lock<std::mutex> lk(S.mu);
-            bool busy = !S.admission.empty();
-            for (auto &sl : S.slots) busy |= sl.busy;
-            for (auto &kv : S.ladders) busy |= kv.second.state == Ladder::BUILDING;
-            if (S.inbox.empty() && !S.stop) S.cv_in.wait_for(lk, std::chrono::microseconds(busy ? 50 : 2000));
+            // A finished query launch is seen on the next pass, so the wait is
+            // short while launches are in flight (it bounds the completion
+            // latency); builds and admission are polled more slowly.
+            bool queries = false, other = !S.admission.empty();
+            for (auto &sl : S.slots) queries |= sl.busy;
+            for (auto &kv : S.ladders) other |= kv.second.state == Ladder::BUILDING;
+            const int wait_us = queries ? 5 : other ? 50 : 2000;
+            if (S.inbox.empty() && !S.stop) S.cv_in.wait_for(lk, std::chrono::microseconds(wait_us));
             if (S.stop) break;
             while (!S.inbox.empty()) {
                 fresh.push_back(S.inbox.front());
