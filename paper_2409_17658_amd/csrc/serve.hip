@@ -1,12 +1,14 @@
 // serve.hip -- a continuous-batching query engine for gamma_R(P_m x C_n).
 //
 // For each m the engine keeps a "ladder" of canonical powers resident in
-// HBM: baby steps A^1 .. A^B (a chain over the compressed rows of the sparse
-// transfer matrix) and giant steps A^B, A^2B, ... (dense products), and
-// answers n = B*i + j (1 <= j <= B) as the trace of A^(B i) (x) A^j, i.e.
-// one HBM-bound trace-of-product pass per query (Corollary 7; the product
-// is never formed).  n <= B is read off the baby traces computed once at
-// build time.
+// HBM: baby steps (A^T)^1 .. (A^T)^B, the transposes of A^1 .. A^B (a chain
+// over the compressed rows of the sparse transfer matrix, transposed), and
+// giant steps A^B, A^2B, ... (A^B by the same chain on A, the rest by dense
+// products), plus byte copies of both when their entries fit; it answers
+// n = B*i + j (1 <= j <= B) as the trace of A^(B i) (x) A^j, i.e. one
+// HBM-bound pass per query reading both operands along rows (Corollary 7;
+// the product is never formed).  n <= B is read off the baby traces
+// computed once at build time.
 //
 // A worker thread owns every HIP call.  Each tick it gathers the requests
 // whose ladder is ready into ONE grouped launch on the query stream (up to
