@@ -455,9 +455,28 @@ def bench_config4(args, mpr, torch):
     stream.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     mpr.graph_destroy(g)
-    mpr.set_batch_config(-1)
     mpr.check_status(st)
     batched = [(N.clone(), R.clone()) for (_, _, N, R) in chains]
+    # the same configuration as a persistent grid (resident workgroups looping over the list)
+    mpr.set_batch_persistent(True)
+    try:
+        mpr.batch_plan(chains, ws, stream)
+        pgrid = mpr.batch_plan_info(ws)[1]
+        g = mpr.batch_graph_create(ws, st, stream)
+        mpr.graph_launch(g, stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mpr.graph_launch(g, stream)
+        stream.synchronize()
+        t_pers = (time.perf_counter() - t0) / reps
+        mpr.graph_destroy(g)
+        mpr.check_status(st)
+        pers_same = all(torch.equal(N.view(torch.int16), b[0].view(torch.int16)) and torch.equal(R, b[1])
+                        for (_, _, N, R), b in zip(chains, batched))
+    finally:
+        mpr.set_batch_persistent(False)
+    mpr.set_batch_config(-1)
     # the plain per-instance path: one chain after another
     t_solo, same = None, None
     if args.per_instance:
@@ -483,6 +502,8 @@ def bench_config4(args, mpr, torch):
             "batched_s": round(t_batch, 3), "per_instance_s": round(t_solo, 3) if t_solo else None,
             "per_instance_gpairs": round(pairs / t_solo / 1e9, 1) if t_solo else None,
             "speedup_vs_per_instance": round(t_solo / t_batch, 2) if t_solo else None,
+            "persistent_form": {"grid": pgrid, "s": round(t_pers, 3), "gpairs": round(pairs / t_pers / 1e9, 1),
+                                "equal": bool(pers_same)},
             "pct_valu_peak": round(100 * pairs / t_batch / 1e9 / valu_peak_gpairs(cus, binfo["arith"]), 2),
             "autotune_s": {str(k): round(v, 3) for k, v in tune.items()},
             "batched_equals_per_instance": None if same is None else bool(same), "input_gen_s": round(gen_s, 1)}

@@ -297,15 +297,24 @@ mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count,
                           void *ws, size_t ws_bytes, mpr_stream stream);
 
 /* Runs a planned batch: resets the work counter with a fill kernel and
- * launches one workgroup per panel, the k-th workgroup to start taking the
- * k-th longest panel (no memset node, no host sync, so the pair can be
- * captured into a HIP graph).  Results land in each N_out / R_out. */
+ * launches the batch kernel, whose workgroups take the panels longest first
+ * with one atomic add each (one workgroup per panel, or a persistent grid;
+ * mpr_set_batch_persistent).  No memset node, no host sync, so the pair can
+ * be captured into a HIP graph.  Results land in each N_out / R_out. */
 mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream stream);
 
 /* Describes the plan held in ws: configuration, workgroups of the grid
- * (one per panel) and number of panels (host ints, any may be NULL).
- * MPR_EINVAL if ws holds no plan. */
+ * (one per panel, or the resident workgroups in the persistent form) and
+ * number of panels (host ints, any may be NULL).  MPR_EINVAL if ws holds no
+ * plan. */
 mpr_status mpr_batch_plan_info(void *ws, int *cfg, int *grid, int *panels);
+
+/* Launch form of the plans made after the call (process-wide): 0 (the
+ * default) one workgroup per panel, 1 a persistent grid of the resident
+ * workgroups, each looping over the work list until it is empty.  Same
+ * results; the per-panel form is faster on MI355X because the CU's wave
+ * arbiter favours older waves.  MPR_EINVAL for other values. */
+mpr_status mpr_set_batch_persistent(int on);
 
 /* Plan + launch. */
 mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count,

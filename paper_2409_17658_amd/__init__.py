@@ -107,6 +107,7 @@ _SIGS = {
     "mpr_set_sparse_arith": (_I, [_I]),
     "mpr_batch_plan_info": (_I, [_P, _P, _P, _P]),
     "mpr_set_batch_config": (_I, [_I]),
+    "mpr_set_batch_persistent": (_I, [_I]),
     "mpr_batch_graph_create": (_I, [_P, _P, _P, _P]),
     "mpr_graph_launch": (_I, [_P, _P]),
     "mpr_graph_destroy": (_I, [_P]),
@@ -484,6 +485,12 @@ def batch_plan_info(ws):
 
 def set_batch_config(cfg: int):
     _ok(lib().mpr_set_batch_config(cfg), "mpr_set_batch_config")
+
+
+def set_batch_persistent(on: bool):
+    """Launch form of later batch plans: one workgroup per panel (default) or
+    a persistent grid of the resident workgroups."""
+    _ok(lib().mpr_set_batch_persistent(1 if on else 0), "mpr_set_batch_persistent")
 
 
 # ---------------------------------------------------------------- tiles / tuning

@@ -6,10 +6,11 @@
 // panel.  The batch is cut into panels of BM rows; a work list of
 // (instance, first row) items, longest first, is consumed by a grid of one
 // workgroup per item, each taking the next item with one atomic add when it
-// starts, so the k-th workgroup to start runs the k-th longest item.  The
-// grid is not persistent on purpose: the CU's wave arbiter favours older
-// waves, so of the workgroups sharing a CU the youngest ones progress
-// slowest (on MI355X, four resident workgroups of the 64-row f16
+// starts, so the k-th workgroup to start runs the k-th longest item.  By
+// default the grid is not persistent (a persistent form, a grid of resident
+// workgroups looping over the list, is kept for comparison and is slower):
+// the CU's wave arbiter favours older waves, so of the workgroups sharing a
+// CU the youngest ones progress slowest (on MI355X, four resident workgroups of the 64-row f16
 // configuration ran at 123, 45, 22 and 16 G pairs/s).  A persistent
 // workgroup never gets older than its neighbours, so the ones that started
 // last kept their long first items to the very end of the launch; with one
@@ -136,21 +137,11 @@ struct BatchWaves {
     static constexpr int value = (T::TM * T::TN <= 32) ? 4 : 2;
 };
 
+// One panel: all e - 1 chain steps of rows [row0, row0 + BM) of one chain.
 template <class T, bool H>
-__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<T>::value)))
-void batch_kernel(const DevChain *__restrict__ chains, const BatchItem *__restrict__ items, int n_items,
-                  int *counter, int32_t *st)
+__device__ __forceinline__ void batch_item(const DevChain *__restrict__ chains, const BatchItem item, u16 *lds,
+                                           uint32_t *rmin, int32_t *st)
 {
-    __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
-    __shared__ uint32_t rmin[T::BM];
-    __shared__ int next;
-    // One workgroup per item: the k-th workgroup to start takes the k-th
-    // longest item.
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = next;
-    if (it >= n_items) return;  // block-uniform; not taken when the grid is the item count
-    const BatchItem item = items[it];
     const DevChain c = chains[item.inst];
     const int64_t n = c.n, r0 = item.row0;
     const int rows = (int)min<int64_t>(T::BM, n - r0);
@@ -251,6 +242,30 @@ void batch_kernel(const DevChain *__restrict__ chains, const BatchItem *__restri
     }
 }
 
+template <class T, bool H>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(BatchWaves<T>::value)))
+void batch_kernel(const DevChain *__restrict__ chains, const BatchItem *__restrict__ items, int n_items,
+                  int *counter, int persistent, int32_t *st)
+{
+    __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
+    __shared__ uint32_t rmin[T::BM];
+    __shared__ int next;
+    // Each workgroup takes the next item with one atomic add, so the k-th item
+    // taken is the k-th longest.  One workgroup per item by default; in the
+    // persistent form a grid of resident workgroups loops until the list is
+    // empty.
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();  // every thread has read `next` before it changes
+        if (it >= n_items) return;  // block-uniform
+        batch_item<T, H>(chains, items[it], lds, rmin, st);
+        if (!persistent) return;
+        __syncthreads();  // the next item reuses lds and rmin
+    }
+}
+
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
 
 // ------------------------------------------------------------ host side
@@ -274,6 +289,7 @@ struct BatchPlan {
     int cfg;
     int n_items;
     int grid;
+    int persistent;
     DevChain *chains;
     BatchItem *items;
     int *counter;
@@ -376,6 +392,7 @@ static int choose_batch_cfg(const mpr_chain_desc *d, int count)
 }
 
 static int g_forced_batch_cfg = -1;
+static int g_batch_persistent = 0;
 
 }  // namespace mpr
 
@@ -389,6 +406,13 @@ extern "C" mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threa
     if (panel_rows) *panel_rows = kBatchCfgs[cfg].bm;
     if (threads) *threads = kBatchCfgs[cfg].nt;
     if (arith) *arith = kBatchCfgs[cfg].arith;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_set_batch_persistent(int on)
+{
+    if (on != 0 && on != 1) return MPR_EINVAL;
+    g_batch_persistent = on;
     return MPR_OK;
 }
 
@@ -457,7 +481,9 @@ extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count
     BatchPlan plan;
     plan.cfg = cfg;
     plan.n_items = (int)flat.size();
-    plan.grid = std::max(1, plan.n_items);
+    plan.persistent = g_batch_persistent;
+    plan.grid = plan.persistent ? std::max(1, std::min(plan.n_items, device_cu_count() * occupancy(cfg)))
+                                : std::max(1, plan.n_items);
     plan.chains = (DevChain *)(base + L.chains_off);
     plan.items = (BatchItem *)(base + L.items_off);
     plan.counter = (int *)(base + L.counter_off);
@@ -481,7 +507,7 @@ extern "C" mpr_status mpr_batch_launch(void *ws, int32_t *d_status, mpr_stream s
     mpr_status e = check_launch();
     if (e != MPR_OK) return e;
     const void *args_k = kBatchCfgs[p.cfg].kernel;
-    void *args[] = {&p.chains, &p.items, &p.n_items, &p.counter, &d_status};
+    void *args[] = {&p.chains, &p.items, &p.n_items, &p.counter, &p.persistent, &d_status};
     if (hipLaunchKernel(args_k, dim3(p.grid), dim3(kBatchCfgs[p.cfg].nt), args, 0, s) != hipSuccess) return MPR_EHIP;
     return check_launch();
 }

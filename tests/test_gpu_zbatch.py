@@ -113,6 +113,57 @@ def test_batch_graph_replays(mpr):
         mpr.graph_destroy(g)
 
 
+@pytest.mark.parametrize("cfg", [0, 6, 9])
+def test_batch_persistent_form(mpr, cfg):
+    """The persistent grid (resident workgroups looping over the work list)
+    against the one-workgroup-per-panel form and the oracle: 64 chains of
+    N = 2048 give 2048 to 4096 panels, more than the resident workgroups,
+    so persistent workgroups take several panels each; also captured in a
+    graph and replayed."""
+    print("persistent batch cfg", cfg, flush=True)
+    mpr.set_batch_config(cfg)
+    try:
+        n, e, count = 2048, 3, 64
+        chains, mats = [], []
+        for i in range(count):
+            X = synth.random_matrix(n, n, 700 + i, 0, 31, 0.25)
+            mats.append(X)
+            chains.append((mpr.to_device(X), e, mpr.alloc_matrix(n, n), torch.empty(n, dtype=torch.int64, device="cuda")))
+        ws = mpr.workspace(mpr.batch_workspace_size(chains))
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mpr.batch_plan(chains, ws)
+        mpr.batch_launch(ws, st)
+        torch.cuda.synchronize()
+        per_panel = [(N.clone(), R.clone()) for (_, _, N, R) in chains]
+        mpr.set_batch_persistent(True)
+        mpr.batch_plan(chains, ws)
+        _, grid, panels = mpr.batch_plan_info(ws)
+        assert 1 <= grid < panels
+        stream = torch.cuda.Stream()
+        g = mpr.batch_graph_create(ws, st, stream)
+        try:
+            for rep in range(2):
+                for (_, _, N, R) in chains:
+                    N.view(torch.int16).fill_(7)
+                    R.fill_(-1)
+                torch.cuda.synchronize()
+                mpr.graph_launch(g, stream)
+                stream.synchronize()
+                for (_, _, N, R), (Np, Rp) in zip(chains, per_panel):
+                    assert torch.equal(N.view(torch.int16), Np.view(torch.int16)) and torch.equal(R, Rp), rep
+        finally:
+            mpr.graph_destroy(g)
+        assert int(st.item()) == 0
+        rows = [0, 1029, n - 1]
+        for k in (0, count - 1):
+            Nr, Rr = O.chain_rows(O.from_u16(mats[k]), rows, e)
+            N, R = chains[k][2], chains[k][3]
+            assert np.array_equal(N.cpu().numpy()[rows], O.to_u16(Nr)) and np.array_equal(R.cpu().numpy()[rows], Rr)
+    finally:
+        mpr.set_batch_persistent(False)
+        mpr.set_batch_config(-1)
+
+
 def test_batch_full_config4_sampled_rows(mpr):
     """The full batched workload (256 chains, N log-uniform in [256, 4096],
     e in [8, 128], entries U[0,31] with 25% infinity) in the benchmark's
