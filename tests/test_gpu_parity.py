@@ -170,6 +170,28 @@ def test_gemm_full_size_sampled(mpr):
 
 
 # ------------------------------------------------------------------ normalisation / offsets
+def test_autotune_and_tile_table(mpr):
+    """mpr_autotune_gemm times every configuration and names the fastest;
+    a table installed from it routes products to that configuration, whose
+    results still equal the oracle's; the installed table is then restored."""
+    n = 200
+    best, ms = mpr.autotune_gemm(n, reps=2)
+    assert len(ms) == mpr.gemm_config_count() and 0 <= best < len(ms)
+    assert all(t > 0 for t in ms) and ms[best] == min(ms)
+    prev = [mpr.gemm_pick_config(k, k, k) for k in (100, 300, 5000)]
+    try:
+        mpr.set_tile_table([(250, best), (1 << 40, (best + 1) % len(ms))])
+        assert mpr.gemm_pick_config(n, n, n) == best
+        assert mpr.gemm_pick_config(300, 300, 300) == (best + 1) % len(ms)
+        X = synth.random_matrix(n, n, 61, 0, 40, 0.3)
+        Y = synth.random_matrix(n, n, 62, 0, 40, 0.3)
+        C = mpr.minplus_gemm(_dev(mpr, X), _dev(mpr, Y))
+        assert np.array_equal(_host(C), _u16(O.minplus(O.from_u16(X), O.from_u16(Y))))
+    finally:
+        mpr.init(0)  # reinstalls the persisted table
+    assert [mpr.gemm_pick_config(k, k, k) for k in (100, 300, 5000)] == prev
+
+
 def test_normalise_matches_oracle(mpr):
     X = synth.random_matrix(123, 301, 9, 3, 40, 0.3)
     X[7, :] = 0xFFFF
