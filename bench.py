@@ -579,7 +579,7 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "gemm_traffic.json"))
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one MI355X only: this build has no multi-GPU path "
+        print("bench.py measures one MI355X only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

@@ -45,7 +45,8 @@ def tune(sizes=DEFAULT_SIZES, reps: int = 3, path: str = TABLE) -> dict:
 
 
 def load_table(path: str = TABLE) -> bool:
-    """Installs a persisted table if one exists and matches this build."""
+    """Installs a persisted table if one exists and names only configurations
+    the loaded library has."""
     if not os.path.exists(path):
         return False
     with open(path) as f:
