@@ -45,8 +45,8 @@ def tune(sizes=DEFAULT_SIZES, reps: int = 3, path: str = TABLE) -> dict:
 
 
 def load_table(path: str = TABLE) -> bool:
-    """Installs a persisted table if one exists and names only configurations
-    the loaded library has."""
+    """Installs a persisted table if one exists and was tuned on the
+    configurations the loaded library has (same count and shapes)."""
     if not os.path.exists(path):
         return False
     with open(path) as f:
