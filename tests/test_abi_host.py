@@ -119,3 +119,18 @@ def test_binding_rejects_mistyped_buffers(mpr):
         with pytest.raises(ValueError):
             mpr._ld(bad)
     assert mpr._ld(torch.zeros((4, 8), dtype=torch.uint16)[:, :5]) == 8
+
+
+def test_trace_t_binding_checks(mpr):
+    """trace_of_product_t refuses operands with different row strides and
+    mistyped offset vectors on the host, before any library call."""
+    import torch
+
+    X = torch.zeros((8, 8), dtype=torch.uint16)
+    Y = torch.zeros((8, 16), dtype=torch.uint16)[:, :8]
+    with pytest.raises(ValueError):
+        mpr.trace_of_product_t(X, None, Y, None)
+    with pytest.raises(ValueError):
+        mpr.trace_of_product_t(X, torch.zeros(8, dtype=torch.int32), X, None)
+    with pytest.raises(ValueError):
+        mpr.trace_of_product_t(X, None, X, torch.zeros(4, dtype=torch.int64))
