@@ -6,6 +6,7 @@ import math
 import os
 import time
 
+import numpy as np
 import pytest
 
 import oracle as O
@@ -136,3 +137,25 @@ def test_server_large_ladders_mixed_batches(serve, wide_only):
         assert got[k]["gamma"] == alone[(m, n)] == golden_gamma(m, n), (m, n)
     assert st["max_batch_seen"] >= 2
     assert st["narrow_builds"] == (0 if wide_only else 2)
+
+
+def test_server_large_batches(serve):
+    """One launch slot and a burst of 200 queries: batches grow past the 16
+    queries whose descriptors travel in the launch arguments, so both launch
+    forms run; every answer against the oracle."""
+    rng = np.random.default_rng(17)
+    qs = [(int(m), int(n)) for m, n in zip(rng.integers(3, 7, 200), rng.integers(3, 201, 200))]
+    with serve.Server(baby=16, max_n=200, max_batch=256, slots=1, hbm_budget_bytes=8 << 30) as S:
+        for m in range(3, 7):
+            S.query(m, 200)  # build the ladders first
+        for k, (m, n) in enumerate(qs):
+            S.submit(m, n, k)
+        got, t_end = {}, time.monotonic() + 120
+        while len(got) < len(qs) and time.monotonic() < t_end:
+            for r in S.poll(20):
+                got[r["tag"]] = r
+        st = S.stats()
+    assert len(got) == len(qs)
+    for k, (m, n) in enumerate(qs):
+        assert got[k]["status"] == 0 and got[k]["gamma"] == oracle_gamma(m, n), (m, n)
+    assert st["max_batch_seen"] > 16
