@@ -317,7 +317,11 @@ def bench_config3(args, mpr, torch):
         t0 = time.perf_counter()
         mus, lams, cs, trs = mpr.find_period(A, 300, traces=True, slots=8, sparse=True)
         t_per_sp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mue, lame, ce, tre = mpr.find_period(A, 300, traces=True, slots=8, sparse=True, extend=True)
+        t_per_ext = time.perf_counter() - t0
         same_per = (mus, lams, cs) == (mu, lam, c) and bool(np.array_equal(trs, tr))
+        same_ext = (mue, lame, ce) == (mu, lam, c) and bool(np.array_equal(tre, tr))
         ok = None
         if m in goldens:
             g, per = goldens[m]
@@ -328,7 +332,9 @@ def bench_config3(args, mpr, torch):
                     "sparse_chain_300_s": round(t_sp, 4), "sparse_speedup": round(t_chain / t_sp, 2),
                     "sparse_equals_dense": same_sp,
                     "find_period_300_s": round(t_per, 3), "find_period_sparse_300_s": round(t_per_sp, 3),
-                    "sparse_period_same": same_per, "gamma_3_300_match_golden": ok}
+                    "find_period_sparse_to_period_s": round(t_per_ext, 3),
+                    "sparse_period_same": same_per, "extended_traces_same": same_ext,
+                    "gamma_3_300_match_golden": ok}
     tot = sum(299 * float(v["n_states"]) ** 3 for v in per_m.values())
     tt = sum(v["chain_300_s"] for v in per_m.values())
     if args.with_m9:
@@ -390,6 +396,12 @@ def bench_m10(args, mpr, torch):
     mu, lam, c, tr = mpr.find_period(A, kmax, traces=True, ws=ws, sparse=bool(args.m10_sparse))
     t = time.perf_counter() - t0
     print("m10: %d powers in %.1f s, period %s" % (kmax, t, (mu, lam, c)), file=sys.stderr, flush=True)
+    # the same search stopped at the confirming power (Algorithm 2), later traces from the period
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mue, lame, ce, tre = mpr.find_period(A, kmax, traces=True, ws=ws, sparse=bool(args.m10_sparse), extend=True)
+    t_ext = time.perf_counter() - t0
+    print("m10: stopped at the period in %.1f s" % t_ext, file=sys.stderr, flush=True)
     gam = {k: int(tr[k]) for k in range(3, kmax + 1)}
     out = {"metric": "gamma_R(P_10 x C_n): seconds for the m=10 period search (A^1..A^kmax, N=64769)",
            "value": round(t, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False,
@@ -398,7 +410,9 @@ def bench_m10(args, mpr, torch):
            "dense_equivalent_gpairs": round((kmax - 1) * float(n) ** 3 / t / 1e9, 1),
            "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n,
                       "chain_step": "compressed-K (sparse A)" if args.m10_sparse else "dense"},
-           "period": [mu, lam, c], "seconds": round(t, 1), "gamma": gam}
+           "period": [mu, lam, c], "seconds": round(t, 1), "gamma": gam,
+           "to_period_s": round(t_ext, 2),
+           "extended_traces_same": (mue, lame, ce) == (mu, lam, c) and bool(np.array_equal(tre, tr))}
     if mu is not None:
         numer = mpr.period_formula(mu, lam, c, tr[: mu + lam])
         out["formula"] = {"valid_from": mu, "gamma(n)": "(%d n + numer[n mod %d]) / %d" % (c, lam, lam),

@@ -64,6 +64,8 @@ typedef enum {
 #define MPR_CHAIN_SPARSE 2 /* the chain, each step over only the rows of A that
                             * reach each block of output columns */
 #define MPR_PERIOD_SPARSE 1 /* mpr_find_period_ex flag: compressed-K chain steps */
+#define MPR_PERIOD_EXTEND 2 /* mpr_find_period_ex flag: stop at the confirmed
+                               period and extend the traces by it */
 
 /* Arithmetic of a product configuration.  MPR_ARITH_U16: packed uint16
  * saturating add and min.  MPR_ARITH_F16: the operands' f16 images (a
@@ -263,7 +265,12 @@ mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t 
 
 /* mpr_find_period with flags: MPR_PERIOD_SPARSE runs the chain steps as
  * MPR_CHAIN_SPARSE does (identical results).  The workspace must then be
- * sized by mpr_period_workspace_size_ex with the same flags. */
+ * sized by mpr_period_workspace_size_ex with the same flags.
+ * MPR_PERIOD_EXTEND stops at the power that confirms the period (k = mu +
+ * lambda, as Algorithm 2 does) instead of computing every power to kmax,
+ * and fills traces_host[k] for mu + lambda < k <= kmax from the relation
+ * A^(k) = c (x) A^(k - lambda), k - lambda >= mu (Lemma 2):
+ * trace(k) = trace(k - lambda) + c, exact (MPR_ROW_NONE stays). */
 mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host);
 mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int flags,
                               int64_t *mu_host, int64_t *lam_host, int64_t *c_host, int64_t *traces_host,

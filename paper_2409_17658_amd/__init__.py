@@ -31,6 +31,7 @@ CHAIN = 0
 SQUARE = 1
 CHAIN_SPARSE = 2
 PERIOD_SPARSE = 1
+PERIOD_EXTEND = 2
 ARITH_U16 = 0
 ARITH_F16 = 1
 
@@ -370,12 +371,15 @@ def period_workspace_size(n: int, slots: int, flags: int = 0) -> int:
     return nb.value
 
 
-def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None, sparse: bool = False):
+def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None, sparse: bool = False,
+                extend: bool = False):
     """(mu, lam, c, traces) with traces[k] = trace of A^k for k = 1..kmax
     (None when traces=False); mu is None when no period is confirmed.
-    sparse=True runs the chain steps over the compressed rows of A."""
+    sparse=True runs the chain steps over the compressed rows of A;
+    extend=True stops at the confirming power and fills the later traces
+    from the period (exact)."""
     n = A.shape[0]
-    flags = PERIOD_SPARSE if sparse else 0
+    flags = (PERIOD_SPARSE if sparse else 0) | (PERIOD_EXTEND if extend else 0)
     if ws is None:
         ws = workspace(period_workspace_size(n, slots, flags), A.device)
     mu, lam, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

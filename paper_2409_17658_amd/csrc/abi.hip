@@ -417,7 +417,7 @@ extern "C" mpr_status mpr_trace_of_product_t(const uint16_t *X, const int64_t *R
 
 extern "C" mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host)
 {
-    if (n < 0 || slots < 2 || !bytes_host || (flags & ~MPR_PERIOD_SPARSE)) return MPR_EINVAL;
+    if (n < 0 || slots < 2 || !bytes_host || (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND))) return MPR_EINVAL;
     PeriodWs w = carve_period(nullptr, n, 0, slots, flags);
     *bytes_host = w.fixed + (size_t)slots * w.slot_bytes;
     return MPR_OK;
@@ -433,7 +433,7 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
                                          void *ws, size_t ws_bytes, mpr_stream stream)
 {
     if (n < 1 || kmax < 1 || !A || !mu_host || !lam_host || !c_host || !ld_ok(lda, n)) return MPR_EINVAL;
-    if (flags & ~MPR_PERIOD_SPARSE) return MPR_EINVAL;
+    if (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND)) return MPR_EINVAL;
     const bool sparse = (flags & MPR_PERIOD_SPARSE) != 0;
     PeriodWs w = carve_period(ws, n, ws_bytes, 0, flags);
     if (!ws || w.slots < 2) return MPR_ENOMEM;
@@ -502,6 +502,11 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
             if (!found) seen.emplace(h, k);
         }
         if (found && !traces_host) break;
+        if (found && (flags & MPR_PERIOD_EXTEND)) {
+            for (int64_t j = k + 1; j <= kmax; j++)
+                traces_host[j] = traces_host[j - lam] == MPR_ROW_NONE ? MPR_ROW_NONE : traces_host[j - lam] + cval;
+            break;
+        }
     }
     if (!found) return MPR_ENOTFOUND;
     *mu_host = mu;

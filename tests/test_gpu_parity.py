@@ -467,9 +467,13 @@ def test_config1_gamma_m3(mpr):
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
-def test_find_period_small_m(mpr, m):
+@pytest.mark.parametrize("extend", [False, True])
+def test_find_period_small_m(mpr, m, extend):
+    """Every trace to k = 60 against the oracle, computed power by power or,
+    with extend, computed up to the confirming power and extended by the
+    period after it."""
     A = mpr.build_transfer(m)
-    mu, lam, c, tr = mpr.find_period(A, 60, traces=True)
+    mu, lam, c, tr = mpr.find_period(A, 60, traces=True, extend=extend)
     omu, olam, oc, og = O.find_period(O.transfer(m), 60)
     assert (mu, lam, c) == (omu, olam, oc)
     for k in range(1, 61):
@@ -510,9 +514,16 @@ def test_tiny_and_degenerate_powers_and_periods(mpr):
                 assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), (A, e, schedule)
         mu, lam, c, tr = O.find_period(A, 12)
         for sparse in (False, True):
-            got = mpr.find_period(Ad, 12, traces=True, slots=8, sparse=sparse)
-            assert got[:3] == (mu, lam, c), (A.tolist(), got[:3], (mu, lam, c), sparse)
-            assert all(got[3][k] == tr[k] for k in tr), (A.tolist(), sparse)
+            for extend in (False, True):
+                got = mpr.find_period(Ad, 12, traces=True, slots=8, sparse=sparse, extend=extend)
+                assert got[:3] == (mu, lam, c), (A.tolist(), got[:3], (mu, lam, c), sparse, extend)
+                assert all(got[3][k] == tr[k] for k in tr), (A.tolist(), sparse, extend)
+                if mu is not None:  # every k <= 12, beyond the oracle's own powers by the period
+                    for k in range(1, 13):
+                        ref = tr[k] if k in tr else tr[mu + (k - mu) % lam]
+                        if k not in tr and ref != O.INF:
+                            ref += c * ((k - mu) // lam)
+                        assert got[3][k] == ref, (A.tolist(), k, sparse, extend)
 
 
 def test_find_period_not_found(mpr):
