@@ -20,6 +20,7 @@
 // keeps the running row minima in LDS, then rewrites the slice normalised.
 // Only workgroup barriers separate the phases: no data crosses workgroups.
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -391,8 +392,10 @@ static int choose_batch_cfg(const mpr_chain_desc *d, int count)
     return best;
 }
 
-static int g_forced_batch_cfg = -1;
-static int g_batch_persistent = 0;
+// Process-wide settings, read when a plan is made (atomic: set and read from
+// any thread).
+static std::atomic<int> g_forced_batch_cfg{-1};
+static std::atomic<int> g_batch_persistent{0};
 
 }  // namespace mpr
 
@@ -451,7 +454,8 @@ extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count
     if (e != MPR_OK) return e;
     if (!ws) return MPR_EINVAL;
     if ((e = ensure_init()) != MPR_OK) return e;
-    const int cfg = g_forced_batch_cfg >= 0 ? g_forced_batch_cfg : choose_batch_cfg(descs_host, count);
+    const int forced = g_forced_batch_cfg.load();
+    const int cfg = forced >= 0 ? forced : choose_batch_cfg(descs_host, count);
     const int bm = kBatchCfgs[cfg].bm;
     BatchLayout L = batch_layout(descs_host, count, bm);
     if (ws_bytes < L.bytes) return MPR_ENOMEM;

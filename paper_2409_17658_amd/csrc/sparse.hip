@@ -12,6 +12,7 @@
 // step runs the shared tile routine with the left operand gathered through
 // L_J.  The result is the same product, entry for entry.
 #include <algorithm>
+#include <atomic>
 
 #include "tile.h"
 
@@ -259,7 +260,7 @@ mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hi
     return check_launch();
 }
 
-static int g_sparse_arith = MPR_ARITH_F16;
+static std::atomic<int> g_sparse_arith{MPR_ARITH_F16};  // process-wide, set from any thread
 
 mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s)
 {
