@@ -134,3 +134,27 @@ def test_trace_t_binding_checks(mpr):
         mpr.trace_of_product_t(X, torch.zeros(8, dtype=torch.int32), X, None)
     with pytest.raises(ValueError):
         mpr.trace_of_product_t(X, None, X, torch.zeros(4, dtype=torch.int64))
+
+
+def test_tile_table_loader_checks_configurations(mpr, tmp_path):
+    """A persisted table is installed only when it was tuned on the
+    configurations the loaded library has."""
+    import json
+
+    from paper_2409_17658_amd import autotune
+
+    cfgs = [mpr.gemm_config_info(c) for c in range(mpr.gemm_config_count())]
+    good = {"configs": cfgs, "measurements": [], "table": [[500, 3], [1 << 62, 1]]}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(good))
+    try:
+        assert autotune.load_table(str(p))
+        assert mpr.gemm_pick_config(400, 400, 400) == 3 and mpr.gemm_pick_config(600, 600, 600) == 1
+        for bad in ({**good, "configs": cfgs[:-1]},
+                    {**good, "configs": [dict(cfgs[0], bm=cfgs[0]["bm"] * 2)] + cfgs[1:]}):
+            p.write_text(json.dumps(bad))
+            assert not autotune.load_table(str(p))
+            assert mpr.gemm_pick_config(400, 400, 400) == 3  # the installed table stays
+        assert not autotune.load_table(str(tmp_path / "missing.json"))
+    finally:
+        autotune.load_table()  # the persisted table again

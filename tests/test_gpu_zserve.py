@@ -159,3 +159,17 @@ def test_server_large_batches(serve):
     for k, (m, n) in enumerate(qs):
         assert got[k]["status"] == 0 and got[k]["gamma"] == oracle_gamma(m, n), (m, n)
     assert st["max_batch_seen"] > 16
+
+
+@pytest.mark.parametrize("wide_only", [False, True])
+def test_server_resident_bytes(serve, wide_only):
+    """The bytes a ladder holds, as the server accounts them, are the ones
+    mpr_server_ladder_bytes states (with and without the byte copies)."""
+    with serve.Server(baby=8, max_n=64, max_batch=8, slots=1, hbm_budget_bytes=4 << 30, wide_only=wide_only) as S:
+        S.query(6, 40)
+        b6 = S.stats()["resident_bytes"]
+        S.query(5, 40)
+        b56 = S.stats()["resident_bytes"]
+    assert b6 == serve.ladder_bytes(6, 8, 64, wide_only)
+    assert b56 - b6 == serve.ladder_bytes(5, 8, 64, wide_only)
+    assert serve.ladder_bytes(6, 8, 64, False) > serve.ladder_bytes(6, 8, 64, True)
