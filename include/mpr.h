@@ -364,6 +364,10 @@ typedef struct {
                                  answer from them when every finite entry is
                                  <= 127 (half the bytes per query; exact);
                                  1: uint16 only */
+    int busy_poll;            /* 1: the worker thread never sleeps (one CPU core
+                                 busy; a request is picked up without a thread
+                                 wake-up); 0: it sleeps until a request or a
+                                 launch needs it */
 } mpr_server_options;
 
 typedef struct {

@@ -54,7 +54,7 @@ class ChainDesc(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("baby", ctypes.c_int), ("max_n", ctypes.c_int64),
                 ("max_batch", ctypes.c_int), ("slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("wide_only", ctypes.c_int)]
+                ("wide_only", ctypes.c_int), ("busy_poll", ctypes.c_int)]
 
 
 class QueryResult(ctypes.Structure):

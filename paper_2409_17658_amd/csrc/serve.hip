@@ -399,7 +399,15 @@ static void worker_main(Server *Sp)
             for (auto &sl : S.slots) queries |= sl.busy;
             for (auto &kv : S.ladders) other |= kv.second.state == Ladder::BUILDING;
             const int wait_us = queries ? 5 : other ? 50 : 2000;
-            if (S.inbox.empty() && !S.stop) S.cv_in.wait_for(lk, std::chrono::microseconds(wait_us));
+            if (S.inbox.empty() && !S.stop) {
+                if (S.opt.busy_poll) {
+                    lk.unlock();
+                    std::this_thread::yield();
+                    lk.lock();
+                } else {
+                    S.cv_in.wait_for(lk, std::chrono::microseconds(wait_us));
+                }
+            }
             if (S.stop) break;
             while (!S.inbox.empty()) {
                 fresh.push_back(S.inbox.front());

@@ -15,8 +15,10 @@ from . import MprError, QueryResult, ServerOptions, ServerStats, lib
 
 class Server:
     def __init__(self, device: int = 0, baby: int = 32, max_n: int = 1000, max_batch: int = 256,
-                 slots: int = 4, hbm_budget_bytes: int = 200 << 30, wide_only: bool = False):
-        self.opt = ServerOptions(device, baby, max_n, max_batch, slots, hbm_budget_bytes, int(bool(wide_only)))
+                 slots: int = 4, hbm_budget_bytes: int = 200 << 30, wide_only: bool = False,
+                 busy_poll: bool = False):
+        self.opt = ServerOptions(device, baby, max_n, max_batch, slots, hbm_budget_bytes, int(bool(wide_only)),
+                                 int(bool(busy_poll)))
         h = ctypes.c_void_p()
         st = lib().mpr_server_create(ctypes.byref(self.opt), ctypes.byref(h))
         if st != 0:

@@ -173,3 +173,12 @@ def test_server_resident_bytes(serve, wide_only):
     assert b6 == serve.ladder_bytes(6, 8, 64, wide_only)
     assert b56 - b6 == serve.ladder_bytes(5, 8, 64, wide_only)
     assert serve.ladder_bytes(6, 8, 64, False) > serve.ladder_bytes(6, 8, 64, True)
+
+
+def test_server_busy_poll(serve):
+    """The busy-polling worker answers the same as the sleeping one."""
+    qs = synth.poisson_queries(400.0, 120, seed=9, m_range=(2, 6), n_range=(3, 120))
+    with serve.Server(baby=16, max_n=120, max_batch=64, slots=2, hbm_budget_bytes=4 << 30, busy_poll=True) as S:
+        res = serve.run_open_loop(S, qs, timeout_s=120)
+    for (_, m, n), r in zip(qs, res):
+        assert r["status"] == 0 and r["gamma"] == oracle_gamma(m, n), (m, n)
