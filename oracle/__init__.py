@@ -93,6 +93,10 @@ def lib():
         L.oracle_brute_border_loss.argtypes = [ctypes.c_int, ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_threads.argtypes = []
+        L.oracle_minplus_rows.restype = ctypes.c_int
+        L.oracle_minplus_rows.argtypes = [i64, i64, i64, p, p, p, p, p]
+        L.oracle_transfer_arcs.restype = ctypes.c_int
+        L.oracle_transfer_arcs.argtypes = [ctypes.c_int, p, p, p, p]
         L.oracle_rowdp_gamma.restype = i64
         L.oracle_rowdp_gamma.argtypes = [ctypes.c_int, ctypes.c_int]
         _lib = L
@@ -175,6 +179,45 @@ def minplus(X, Y) -> np.ndarray:
     return C
 
 
+def finite_rows(Y):
+    """The finite entries of Y row by row: (start, col, val) with row k's
+    columns col[start[k]:start[k+1]] (ascending) and values val[...]; the
+    shape's column count rides along as the fourth element."""
+    Y = _c64(Y)
+    fin = Y != INF
+    start = np.concatenate([[0], np.cumsum(fin.sum(axis=1))]).astype(np.int64)
+    rr, cc = np.nonzero(fin)
+    return start, cc.astype(np.int32), Y[rr, cc].astype(np.int64), Y.shape[1]
+
+
+def minplus_rows(X, Yrows) -> np.ndarray:
+    """X (x) Y (Section 3) with Y given by finite_rows() / transfer_arcs():
+    the same definition, the infinite entries of Y never visited."""
+    X = _c64(X)
+    start, col, val, N = Yrows
+    M, K = X.shape
+    if len(start) != K + 1:
+        raise ValueError("inner dimensions differ")
+    C = np.empty((M, N), dtype=np.int64)
+    lib().oracle_minplus_rows(M, K, N, _ptr(X), _ptr(start), _ptr(col), _ptr(val), _ptr(C))
+    return C
+
+
+def transfer_arcs(m: int):
+    """A(G) of Corollary 7 by its finite entries (finite_rows() layout),
+    for m whose dense matrix is too large (m = 10: 64769 states)."""
+    n = len(words(m))
+    count = np.empty(n, dtype=np.int64)
+    if lib().oracle_transfer_arcs(m, _ptr(count), None, None, None) != 0:
+        raise RuntimeError("oracle_transfer_arcs failed")
+    start = np.concatenate([[0], np.cumsum(count)]).astype(np.int64)
+    col = np.empty(int(start[-1]), dtype=np.int32)
+    val = np.empty(int(start[-1]), dtype=np.int64)
+    if lib().oracle_transfer_arcs(m, None, _ptr(start), _ptr(col), _ptr(val)) != 0:
+        raise RuntimeError("oracle_transfer_arcs failed")
+    return start, col, val, n
+
+
 def minplus_at(X, Y, ii, jj) -> np.ndarray:
     """Entries (ii[t], jj[t]) of X (x) Y, each from the definition alone."""
     X, Y = _c64(X), _c64(Y)
@@ -246,6 +289,21 @@ def chain_rows(A, rows, e: int):
     for _ in range(2, e + 1):
         N, r = normalise(minplus(N, A))
         R = add_offsets(R, r)
+    return N, R
+
+
+def chain_rows_sparse(first_rows, Arows, e: int, on_step=None):
+    """chain_rows with A given by its finite entries (transfer_arcs() or
+    finite_rows()) and its rows `rows` given as first_rows (e.g. from
+    transfer_rows()); on_step(k, N_k, R_k) for every k = 1..e when given."""
+    N, R = normalise(first_rows)
+    if on_step:
+        on_step(1, N, R)
+    for k in range(2, e + 1):
+        N, r = normalise(minplus_rows(N, Arows))
+        R = add_offsets(R, r)
+        if on_step:
+            on_step(k, N, R)
     return N, R
 
 

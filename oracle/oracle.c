@@ -141,10 +141,34 @@ int oracle_transfer(int m, int64_t *A)
 /* (min,+) product, Section 3: c_ij = min_k (x_ik + y_kj), taken over  */
 /* the k for which both entries are finite; infinite if there is none. */
 /* ------------------------------------------------------------------ */
+/* The same product with Y given by its finite entries only, row by row:
+ * row k of Y holds the values val[t] in the columns col[t] for
+ * start[k] <= t < start[k + 1]; every other entry of Y is infinite.
+ * Skipping infinite entries is the definition's "over the k for which both
+ * entries are finite", nothing more. */
+int oracle_minplus_rows(int64_t M, int64_t K, int64_t N, const int64_t *X,
+                        const int64_t *start, const int32_t *col, const int64_t *val, int64_t *C)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < M; i++) {
+        int64_t *c = C + i * N;
+        for (int64_t j = 0; j < N; j++) c[j] = ORACLE_INF;
+        for (int64_t k = 0; k < K; k++) {
+            int64_t x = X[i * K + k];
+            if (x == ORACLE_INF) continue;
+            for (int64_t t = start[k]; t < start[k + 1]; t++) {
+                int64_t s = x + val[t];
+                if (s < c[col[t]]) c[col[t]] = s;
+            }
+        }
+    }
+    return 0;
+}
+
 int oracle_minplus(int64_t M, int64_t K, int64_t N,
                    const int64_t *X, const int64_t *Y, int64_t *C)
 {
-    /* The finite entries of each row of Y, listed once (column indices). */
+    /* The finite entries of each row of Y, listed once. */
     int64_t *start = (int64_t *)malloc((size_t)(K + 1) * sizeof(int64_t));
     if (!start) return -2;
     start[0] = 0;
@@ -154,31 +178,23 @@ int oracle_minplus(int64_t M, int64_t K, int64_t N,
             if (Y[k * N + j] != ORACLE_INF) c++;
         start[k + 1] = start[k] + c;
     }
-    int32_t *col = (int32_t *)malloc((size_t)(start[K] > 0 ? start[K] : 1) * sizeof(int32_t));
-    if (!col) { free(start); return -2; }
+    const size_t nnz = (size_t)(start[K] > 0 ? start[K] : 1);
+    int32_t *col = (int32_t *)malloc(nnz * sizeof(int32_t));
+    int64_t *val = (int64_t *)malloc(nnz * sizeof(int64_t));
+    if (!col || !val) { free(col); free(val); free(start); return -2; }
     for (int64_t k = 0; k < K; k++) {
         int64_t t = start[k];
         for (int64_t j = 0; j < N; j++)
-            if (Y[k * N + j] != ORACLE_INF) col[t++] = (int32_t)j;
-    }
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t i = 0; i < M; i++) {
-        int64_t *c = C + i * N;
-        for (int64_t j = 0; j < N; j++) c[j] = ORACLE_INF;
-        for (int64_t k = 0; k < K; k++) {
-            int64_t x = X[i * K + k];
-            if (x == ORACLE_INF) continue;
-            const int64_t *y = Y + k * N;
-            for (int64_t t = start[k]; t < start[k + 1]; t++) {
-                int64_t j = col[t];
-                int64_t s = x + y[j];
-                if (s < c[j]) c[j] = s;
+            if (Y[k * N + j] != ORACLE_INF) {
+                col[t] = (int32_t)j;
+                val[t++] = Y[k * N + j];
             }
-        }
     }
+    int rc = oracle_minplus_rows(M, K, N, X, start, col, val, C);
+    free(val);
     free(col);
     free(start);
-    return 0;
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */
@@ -400,6 +416,37 @@ int oracle_transfer_rows(int m, const int64_t *rows, int64_t count, int64_t *out
             const uint8_t *q = w + rows[t] * m, *p = w + pi * m;
             out[t * n + pi] = oracle_follows(q, p, m) ? column_weight(p, m) : ORACLE_INF;
         }
+    free(w);
+    return 0;
+}
+
+/* A(G) of Corollary 7 by its finite entries (the arcs), row by row, for
+ * sizes whose dense matrix would not fit: the same double loop over (q, p)
+ * and the same rule and weight as oracle_transfer.  First call with
+ * col == NULL: count[q] = number of p that can follow q.  Second call with
+ * start[q] = sum of the counts before q: the columns p (ascending) and the
+ * weights of row q go to col / val from start[q] on. */
+int oracle_transfer_arcs(int m, int64_t *count, const int64_t *start, int32_t *col, int64_t *val)
+{
+    int64_t n = oracle_words(m, NULL);
+    if (n < 0) return -1;
+    uint8_t *w = (uint8_t *)malloc((size_t)(n * m));
+    if (!w) return -2;
+    oracle_words(m, w);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t qi = 0; qi < n; qi++) {
+        int64_t t = col ? start[qi] : 0;
+        for (int64_t pi = 0; pi < n; pi++) {
+            const uint8_t *q = w + qi * m, *p = w + pi * m;
+            if (!oracle_follows(q, p, m)) continue;
+            if (col) {
+                col[t] = (int32_t)pi;
+                val[t] = column_weight(p, m);
+            }
+            t++;
+        }
+        if (!col) count[qi] = t;
+    }
     free(w);
     return 0;
 }

@@ -315,6 +315,51 @@ def test_entrywise_and_row_restricted_helpers():
     assert np.array_equal(O.transfer_rows(5, [0, 7, 286]), T[[0, 7, 286]])
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 2), (7, 4, 9), (16, 16, 16), (5, 31, 3)])
+def test_listed_product_matches_triple_loop(shape):
+    """The product over a right operand given by its finite entries, against
+    the pure-Python triple loop (an all-infinite row and column included)."""
+    M, K, N = shape
+    X = O.from_u16(synth.random_matrix(M, K, 51, 0, 9, 0.3))
+    Y = O.from_u16(synth.random_matrix(K, N, 52, 0, 9, 0.4))
+    Y[K // 2, :] = INF
+    Y[:, N // 2] = INF
+    assert O.minplus_rows(X, O.finite_rows(Y)).tolist() == _py_minplus(X.tolist(), Y.tolist())
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7])
+def test_transfer_arcs_are_the_finite_entries(m):
+    """The arc lists equal the finite entries of the whole matrix (whose
+    entries are pinned by exhaustive search and the row DP)."""
+    start, col, val, n = O.transfer_arcs(m)
+    fs, fc, fv, fn = O.finite_rows(O.transfer(m))
+    assert n == fn and np.array_equal(start, fs) and np.array_equal(col, fc) and np.array_equal(val, fv)
+
+
+def test_transfer_arc_counts():
+    """Arc counts nnz(A) for m = 1..9 (counted from the rule lists; m = 8
+    and 9 without the dense matrix), and every state has an arc out."""
+    want = [7, 33, 167, 836, 4195, 21043, 105566, 529584, 2656733]
+    for m, nnz in enumerate(want, start=1):
+        start, _, _, n = O.transfer_arcs(m)
+        assert start[-1] == nnz and n == len(O.words(m)) and np.all(np.diff(start) >= 1), m
+
+
+def test_sparse_chain_rows_equal_the_dense_chain():
+    """Rows of A^k followed through the arc lists equal the rows of the
+    whole-matrix chain, for every k."""
+    m, e, rows = 6, 25, [0, 1, 400, 847]
+    A = O.transfer(m)
+    seen = {}
+    O.chain_rows_sparse(O.transfer_rows(m, rows), O.transfer_arcs(m), e,
+                        on_step=lambda k, N, R: seen.__setitem__(k, (N.copy(), R.copy())))
+
+    def check(k, N, R):
+        assert np.array_equal(seen[k][0], N[rows]) and np.array_equal(seen[k][1], R[rows]), k
+
+    O.power_chain(A, e, on_step=check)
+
+
 def _raw_period_brute(A, K=12):
     """Least (mu, lam) and a c with A^(mu+lam) = c (x) A^mu, from raw powers
     (the definition, no canonical forms); c = 0 when A^mu has no finite entry."""
