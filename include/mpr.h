@@ -131,9 +131,10 @@ mpr_status mpr_build_border_transfer(int m, uint16_t *A, int64_t lda, int64_t *s
  * [0, 0xFFFE].  M, N, K >= 0 (an empty K gives an all-MPR_INF C).  C must
  * not overlap A or B.  Fast path: A, B, C 16-byte aligned and lda, ldb, ldc
  * multiples of 8; any other layout takes a slower element-wise path.  The
- * configuration the tile table picks may compute in the f16 form
- * (MPR_ARITH_F16): the result is the same, but tiles whose minima reach
- * 2048 are computed twice (about 1.75x the uint16 time for such tiles). */
+ * configuration comes from the tile table of the process-wide arithmetic
+ * (mpr_set_arith): packed uint16 by default; in the f16 form the result is
+ * the same, but tiles whose minima reach 2048 are computed twice (about
+ * 1.75x the uint16 time for such tiles). */
 mpr_status mpr_minplus_gemm(int64_t M, int64_t N, int64_t K,
                             const uint16_t *A, int64_t lda,
                             const uint16_t *B, int64_t ldb,
@@ -254,12 +255,15 @@ mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t km
  *   gamma(n) = traces[mu + (n - mu) mod lam] + c * floor((n - mu) / lam)
  * for n >= mu, and traces[n] below mu.  traces_host[k] (k <= kmax) are the
  * traces of A^k as mpr_find_period returns them; needs mu + lam - 1 <= kmax
- * (and n <= kmax when n < mu).  Host only. */
+ * (and n <= kmax when n < mu).  A residue class whose trace is MPR_ROW_NONE
+ * (no closed walk of that length) gives MPR_ROW_NONE for every n in it.
+ * Host only. */
 mpr_status mpr_gamma_from_period(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
                                  int64_t kmax, int64_t n, int64_t *gamma_host);
 /* The same solution as a closed form: for n >= mu,
  *   gamma(n) = (c * n + numer_host[n mod lam]) / lam   (an exact division),
- * numer_host receiving lam int64 values.  Host only. */
+ * numer_host receiving lam int64 values; numer_host[r] = MPR_ROW_NONE when
+ * residue class r has no finite trace.  Host only. */
 mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t *traces_host,
                               int64_t kmax, int64_t *numer_host);
 
@@ -328,9 +332,22 @@ mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count,
                            void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
 
 /* Arithmetic (MPR_ARITH_*) of the compressed-K chain steps of
- * MPR_CHAIN_SPARSE and MPR_PERIOD_SPARSE; MPR_ARITH_F16 by default.  Both
- * give the same powers bit for bit.  Process-wide setting. */
+ * MPR_CHAIN_SPARSE and MPR_PERIOD_SPARSE; MPR_ARITH_U16 by default (and
+ * whatever mpr_set_arith last set).  Both give the same powers bit for
+ * bit.  Process-wide setting. */
 mpr_status mpr_set_sparse_arith(int arith);
+
+/* Process-wide arithmetic (MPR_ARITH_U16, the default, or MPR_ARITH_F16) of
+ * every product whose configuration the library picks: products with
+ * cfg = -1 (the tile table of that arithmetic), the steps of
+ * mpr_minplus_power, mpr_find_period and the server's ladder builds, the
+ * compressed-K steps (as mpr_set_sparse_arith) and the configuration that
+ * mpr_batch_plan chooses.  Results are identical bit for bit in both;
+ * MPR_EINVAL for other values.  Calls already enqueued keep the arithmetic
+ * they were launched with. */
+mpr_status mpr_set_arith(int arith);
+/* The current process-wide arithmetic (MPR_ARITH_*). */
+int mpr_get_arith(void);
 
 /* Number of compiled batched-kernel configurations (panel heights). */
 int mpr_batch_config_count(void);
@@ -338,8 +355,17 @@ int mpr_batch_config_count(void);
  * batched configuration cfg (host ints, any may be NULL). */
 mpr_status mpr_batch_config_info(int cfg, int *panel_rows, int *threads, int *arith);
 /* Forces the configuration later mpr_batch_plan calls use (-1 = choose by
- * a longest-first schedule model of the batch).  Process-wide setting. */
+ * a longest-first schedule model of the batch among the configurations of
+ * the process-wide arithmetic).  Process-wide setting. */
 mpr_status mpr_set_batch_config(int cfg);
+/* Relative throughputs the schedule model weighs each batched
+ * configuration by (count = mpr_batch_config_count(); rel_host[c] > 0, or
+ * 0 to exclude configuration c; each arithmetic must keep one).  The batch
+ * autotuner measures them; rel_host = NULL restores the compiled-in
+ * values.  Process-wide; MPR_EINVAL on a bad count or value. */
+mpr_status mpr_set_batch_weights(const double *rel_host, int count);
+/* Copies the weights in use into rel_host (capacity count). */
+mpr_status mpr_get_batch_weights(double *rel_host, int count);
 
 /* Captures mpr_batch_launch(ws, d_status) on `stream` into an instantiated
  * HIP graph returned in *graph_host (opaque).  Synchronous. */
@@ -427,11 +453,15 @@ int mpr_gemm_config_count(void);
  * ints, any may be NULL). */
 mpr_status mpr_gemm_config_info(int cfg, int *bm, int *bn, int *bk, int *tm, int *tn, int *threads,
                                 int *arith);
-/* The configuration the tile table gives an M x N x K product (cfg = -1). */
+/* The configuration the tile table of the process-wide arithmetic gives an
+ * M x N x K product (cfg = -1). */
 int mpr_gemm_pick_config(int64_t M, int64_t N, int64_t K);
-/* Installs the size -> configuration table used when cfg = -1: entry t
+/* Installs a size -> configuration table used when cfg = -1: entry t
  * applies to problems whose largest dimension is <= max_dim_host[t]
- * (ascending); larger problems use the last entry.  Copies the arrays. */
+ * (ascending); larger problems use the last entry.  Every entry must name
+ * a configuration of one arithmetic, and the table replaces that
+ * arithmetic's table (products use the table of the process-wide
+ * arithmetic, mpr_set_arith).  Copies the arrays. */
 mpr_status mpr_set_tile_table(const int64_t *max_dim_host, const int *cfg_host, int entries);
 /* Times every configuration on an n x n x n product (random operands made
  * inside; allocates, so not for use on a hot path) and writes the average

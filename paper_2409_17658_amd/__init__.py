@@ -106,6 +106,10 @@ _SIGS = {
     "mpr_batch_config_count": (_I, []),
     "mpr_batch_config_info": (_I, [_I, _P, _P, _P]),
     "mpr_set_sparse_arith": (_I, [_I]),
+    "mpr_set_arith": (_I, [_I]),
+    "mpr_get_arith": (_I, []),
+    "mpr_set_batch_weights": (_I, [_P, _I]),
+    "mpr_get_batch_weights": (_I, [_P, _I]),
     "mpr_batch_plan_info": (_I, [_P, _P, _P, _P]),
     "mpr_set_batch_config": (_I, [_I]),
     "mpr_set_batch_persistent": (_I, [_I]),
@@ -225,13 +229,16 @@ def version() -> int:
 
 
 def init(device: int = 0, tile_table: bool = True):
-    """Checks the device and installs the autotuner's persisted tile table
-    (tile_table.json next to the library) when there is one."""
+    """Checks the device and installs the autotuners' persisted tables
+    (tile_table.json: size -> product configuration per arithmetic;
+    batch_table.json: weights of the batched-configuration model) when
+    there are any."""
     _ok(lib().mpr_init(device), "mpr_init")
     if tile_table:
-        from .autotune import load_table
+        from .autotune import load_batch_table, load_table
 
         load_table()
+        load_batch_table()
 
 
 def transfer_size(m: int) -> int:
@@ -475,9 +482,62 @@ def batch_config_info(cfg: int):
     return {"panel_rows": r.value, "threads": t.value, "arith": "f16" if a.value == ARITH_F16 else "u16"}
 
 
+def _arith_code(arith: str) -> int:
+    if arith not in ("u16", "f16"):
+        raise ValueError("arithmetic is 'u16' or 'f16'")
+    return ARITH_F16 if arith == "f16" else ARITH_U16
+
+
 def set_sparse_arith(arith: str):
-    """'f16' (default) or 'u16' for the compressed-K chain steps."""
-    _ok(lib().mpr_set_sparse_arith(ARITH_F16 if arith == "f16" else ARITH_U16), "mpr_set_sparse_arith")
+    """'u16' (default) or 'f16' for the compressed-K chain steps."""
+    _ok(lib().mpr_set_sparse_arith(_arith_code(arith)), "mpr_set_sparse_arith")
+
+
+def set_arith(arith: str):
+    """Process-wide arithmetic of the products the library configures:
+    'u16' (packed uint16, the default) or 'f16' (the exact f16 form)."""
+    _ok(lib().mpr_set_arith(_arith_code(arith)), "mpr_set_arith")
+
+
+def get_arith() -> str:
+    return "f16" if lib().mpr_get_arith() == ARITH_F16 else "u16"
+
+
+class arith_scope:
+    """with arith_scope('f16'): ... -- sets the process-wide arithmetic and
+    restores the previous one (and the u16 compressed-K default) on exit."""
+
+    def __init__(self, arith: str):
+        self.arith = arith
+
+    def __enter__(self):
+        self.prev = get_arith()
+        set_arith(self.arith)
+        return self
+
+    def __exit__(self, *exc):
+        set_arith(self.prev)
+        return False
+
+
+def set_batch_weights(rel=None):
+    """Relative throughput per batched configuration for the schedule model
+    (None: the compiled-in values)."""
+    cnt = batch_config_count()
+    if rel is None:
+        _ok(lib().mpr_set_batch_weights(None, cnt), "mpr_set_batch_weights")
+        return
+    if len(rel) != cnt:
+        raise ValueError("one weight per batched configuration (%d)" % cnt)
+    arr = (ctypes.c_double * cnt)(*[float(x) for x in rel])
+    _ok(lib().mpr_set_batch_weights(arr, cnt), "mpr_set_batch_weights")
+
+
+def get_batch_weights():
+    cnt = batch_config_count()
+    arr = (ctypes.c_double * cnt)()
+    _ok(lib().mpr_get_batch_weights(arr, cnt), "mpr_get_batch_weights")
+    return list(arr)
 
 
 def batch_plan_info(ws):

@@ -526,7 +526,10 @@ extern "C" mpr_status mpr_gamma_from_period(int64_t mu, int64_t lam, int64_t c, 
         return MPR_OK;
     }
     const int64_t q = (n - mu) / lam, r = (n - mu) % lam;
-    *gamma_host = traces_host[mu + r] + c * q;
+    // A residue class whose traces have no finite term stays empty
+    // (trace(k + lam) = c + trace(k) keeps +infinity).
+    const int64_t t = traces_host[mu + r];
+    *gamma_host = t == MPR_ROW_NONE ? MPR_ROW_NONE : t + c * q;
     return MPR_OK;
 }
 
@@ -536,7 +539,8 @@ extern "C" mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, con
     if (mu < 1 || lam < 1 || !traces_host || !numer_host || mu + lam - 1 > kmax) return MPR_EINVAL;
     for (int64_t r = 0; r < lam; r++) {
         const int64_t k = mu + r;  // residue class of k modulo lam
-        numer_host[k % lam] = lam * traces_host[k] - c * k;
+        // an empty residue class (no finite trace) is reported as MPR_ROW_NONE
+        numer_host[k % lam] = traces_host[k] == MPR_ROW_NONE ? MPR_ROW_NONE : lam * traces_host[k] - c * k;
     }
     return MPR_OK;
 }

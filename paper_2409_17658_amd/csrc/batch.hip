@@ -364,26 +364,39 @@ static double panel_cost(const mpr_chain_desc &d, int bm)
 // Relative throughput of each configuration on a full chip (uniform
 // batches of 128 chains of N = 1024, e = 17, measured on MI355X; the f16
 // 64x128 4x8 configuration = 1).  The schedule model below scores load
-// balance; these weigh in how fast each tile shape runs.
+// balance; these weigh in how fast each tile shape runs.  They are the
+// compiled-in prior: the batch autotuner measures its own and installs them
+// with mpr_set_batch_weights.
 static const double kBatchRel[] = {0.79, 0.63, 0.75, 0.69, 0.49, 0.70,   // uint16 0..5
                                    1.00, 0.77, 0.93, 0.86, 0.63, 0.88};  // f16 6..11
 static_assert(sizeof(kBatchRel) / sizeof(kBatchRel[0]) == kNumBatchCfgs, "one prior per configuration");
+static std::mutex g_weights_mu;
+static std::vector<double> g_batch_rel(kBatchRel, kBatchRel + kNumBatchCfgs);
 
-static int choose_batch_cfg(const mpr_chain_desc *d, int count)
+// Configuration of a batch in arithmetic `arith`: the one whose modelled
+// makespan (longest-first schedule of its panels, weighed by the
+// configuration's relative throughput) is least.
+static int choose_batch_cfg(const mpr_chain_desc *d, int count, int arith)
 {
+    std::vector<double> rel;
+    {
+        std::lock_guard<std::mutex> lk(g_weights_mu);
+        rel = g_batch_rel;
+    }
     const int cus = device_cu_count();
-    int best = 0;
+    int best = -1;
     double best_t = 1e300;
     for (int c = 0; c < kNumBatchCfgs; c++) {
+        if (kBatchCfgs[c].arith != arith || !(rel[c] > 0.0)) continue;
         const int bm = kBatchCfgs[c].bm;
         std::vector<double> w;
         for (int i = 0; i < count; i++)
             for (int64_t r0 = 0; r0 < d[i].n; r0 += bm) w.push_back(panel_cost(d[i], bm));
         std::sort(w.begin(), w.end(), std::greater<double>());
-        // A worker's speed is the CU's rate (kBatchRel) shared among its
-        // resident workers.
+        // A worker's speed is the CU's rate (rel) shared among its resident
+        // workers.
         const int per_cu = std::max(1, occupancy(c));
-        const double t = lpt_makespan(w, cus * per_cu) * per_cu / kBatchRel[c];
+        const double t = lpt_makespan(w, cus * per_cu) * per_cu / rel[c];
         if (t < best_t) {
             best_t = t;
             best = c;
@@ -416,6 +429,32 @@ extern "C" mpr_status mpr_set_batch_persistent(int on)
 {
     if (on != 0 && on != 1) return MPR_EINVAL;
     g_batch_persistent = on;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_set_batch_weights(const double *rel_host, int count)
+{
+    if (count != kNumBatchCfgs) return MPR_EINVAL;
+    std::vector<double> w(kBatchRel, kBatchRel + kNumBatchCfgs);
+    if (rel_host) {
+        bool any[2] = {false, false};
+        for (int c = 0; c < count; c++) {
+            if (!(rel_host[c] >= 0.0) || rel_host[c] > 1e6) return MPR_EINVAL;
+            any[kBatchCfgs[c].arith == MPR_ARITH_F16] |= rel_host[c] > 0.0;
+            w[c] = rel_host[c];
+        }
+        if (!any[0] || !any[1]) return MPR_EINVAL;  // every arithmetic keeps a configuration
+    }
+    std::lock_guard<std::mutex> lk(g_weights_mu);
+    g_batch_rel = w;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_get_batch_weights(double *rel_host, int count)
+{
+    if (!rel_host || count < kNumBatchCfgs) return MPR_EINVAL;
+    std::lock_guard<std::mutex> lk(g_weights_mu);
+    for (int c = 0; c < kNumBatchCfgs; c++) rel_host[c] = g_batch_rel[c];
     return MPR_OK;
 }
 
@@ -455,7 +494,7 @@ extern "C" mpr_status mpr_batch_plan(const mpr_chain_desc *descs_host, int count
     if (!ws) return MPR_EINVAL;
     if ((e = ensure_init()) != MPR_OK) return e;
     const int forced = g_forced_batch_cfg.load();
-    const int cfg = forced >= 0 ? forced : choose_batch_cfg(descs_host, count);
+    const int cfg = forced >= 0 ? forced : choose_batch_cfg(descs_host, count, current_arith());
     const int bm = kBatchCfgs[cfg].bm;
     BatchLayout L = batch_layout(descs_host, count, bm);
     if (ws_bytes < L.bytes) return MPR_ENOMEM;

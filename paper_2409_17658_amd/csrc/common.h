@@ -129,6 +129,8 @@ int device_cu_count();
 mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda,
                        const u16 *B, int64_t ldb, u16 *C, int64_t ldc, hipStream_t s);
 int pick_config(int64_t M, int64_t N, int64_t K);
+int pick_config_arith(int arith, int64_t M, int64_t N, int64_t K);
+int current_arith();
 
 // sparse.hip
 size_t sparse_plan_bytes(int64_t n);

@@ -2,6 +2,7 @@
 // compiled tile configurations, the size -> configuration table and the
 // autotuner that fills it.
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -101,19 +102,30 @@ static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0, false), MPR_CFG(Cfg1, false), MPR_
 #undef MPR_CFG
 static constexpr int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 
-// Size -> configuration table (largest dimension, ascending).  The default
-// is replaced by mpr_set_tile_table with the autotuner's measurements.
-static std::mutex g_table_mu;
-static std::vector<std::pair<int64_t, int>> g_table = {{96, 9}, {1024, 6}, {INT64_MAX, 6}};
+// Arithmetic of the products whose configuration the library picks (the
+// tile table, chain and period steps, batched plans, server builds):
+// MPR_ARITH_U16 by default, MPR_ARITH_F16 on request.  Process-wide.
+static std::atomic<int> g_arith{MPR_ARITH_U16};
+int current_arith() { return g_arith.load(); }
 
-int pick_config(int64_t M, int64_t N, int64_t K)
+// Size -> configuration tables (largest dimension, ascending), one per
+// arithmetic.  The defaults are replaced by mpr_set_tile_table with the
+// autotuner's measurements.
+static std::mutex g_table_mu;
+static std::vector<std::pair<int64_t, int>> g_table[2] = {{{96, 3}, {1024, 0}, {INT64_MAX, 0}},
+                                                          {{96, 9}, {1024, 6}, {INT64_MAX, 6}}};
+
+int pick_config_arith(int arith, int64_t M, int64_t N, int64_t K)
 {
     const int64_t d = std::max(M, std::max(N, K));
     std::lock_guard<std::mutex> lk(g_table_mu);
-    for (auto &e : g_table)
+    const auto &t = g_table[arith == MPR_ARITH_F16 ? 1 : 0];
+    for (auto &e : t)
         if (d <= e.first) return e.second;
-    return g_table.back().second;
+    return t.back().second;
 }
+
+int pick_config(int64_t M, int64_t N, int64_t K) { return pick_config_arith(current_arith(), M, N, K); }
 
 mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
                        int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
@@ -157,15 +169,27 @@ extern "C" mpr_status mpr_set_tile_table(const int64_t *max_dim_host, const int 
 {
     if (entries <= 0 || !max_dim_host || !cfg_host) return MPR_EINVAL;
     std::vector<std::pair<int64_t, int>> t;
+    int arith = -1;
     for (int i = 0; i < entries; i++) {
         if (cfg_host[i] < 0 || cfg_host[i] >= kNumCfgs) return MPR_EINVAL;
         if (i > 0 && max_dim_host[i] <= max_dim_host[i - 1]) return MPR_EINVAL;
+        if (arith >= 0 && kCfgs[cfg_host[i]].arith != arith) return MPR_EINVAL;  // one arithmetic per table
+        arith = kCfgs[cfg_host[i]].arith;
         t.push_back({max_dim_host[i], cfg_host[i]});
     }
     std::lock_guard<std::mutex> lk(g_table_mu);
-    g_table = t;
+    g_table[arith == MPR_ARITH_F16 ? 1 : 0] = t;
     return MPR_OK;
 }
+
+extern "C" mpr_status mpr_set_arith(int arith)
+{
+    if (arith != MPR_ARITH_U16 && arith != MPR_ARITH_F16) return MPR_EINVAL;
+    g_arith = arith;
+    return mpr_set_sparse_arith(arith);
+}
+
+extern "C" int mpr_get_arith(void) { return current_arith(); }
 
 __global__ void tune_fill_kernel(u16 *X, int64_t count, uint64_t seed)
 {

@@ -343,22 +343,55 @@ static void complete(Server &S, const Request &r, int64_t gamma, int status, dou
     S.cv_out.notify_all();
 }
 
-// Try to admit ladder m; evicts idle ladders LRU.  True when building.
+// Device memory free right now (0 if it can not be read).
+static size_t free_device_bytes()
+{
+    size_t fr = 0, total = 0;
+    if (hipMemGetInfo(&fr, &total) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return fr;
+}
+
+// Headroom kept free on the device beyond a ladder's own bytes.
+constexpr size_t kFreeMargin = (size_t)256 << 20;
+
+// Try to admit ladder m; evicts idle ladders LRU until the ladder fits both
+// the byte budget and the device's free memory.  True when building (or
+// failed, the failure recorded for the waiting requests); false when it
+// must wait for memory that a running build or query will release.
 static bool admit(Server &S, int m)
 {
     const int B = S.opt.baby, G = giant_count(S.opt);
     const size_t need = ladder_bytes(m, B, G, !S.opt.wide_only, nullptr, nullptr);
     if (need > S.opt.hbm_budget_bytes) return false;
-    while (S.resident + need > S.opt.hbm_budget_bytes) {
+    for (;;) {
+        const bool budget_ok = S.resident + need <= S.opt.hbm_budget_bytes;
+        const bool free_ok = need + kFreeMargin <= free_device_bytes();
+        if (budget_ok && free_ok) break;
         Ladder *victim = nullptr;
+        bool busy = false;  // some ladder of this server will release memory later
         for (auto &kv : S.ladders) {
             Ladder &L = kv.second;
+            busy |= L.state == Ladder::BUILDING || (L.state == Ladder::READY && L.inflight > 0);
             if (L.state != Ladder::READY || L.inflight > 0 || !S.waiting[kv.first].empty()) continue;
             if (!victim || L.last_use < victim->last_use) victim = &L;
         }
-        if (!victim) return false;
-        free_ladder(S, *victim);
-        stats_update(S, [](mpr_server_stats &t) { t.evictions++; });
+        if (victim) {
+            free_ladder(S, *victim);
+            stats_update(S, [](mpr_server_stats &t) { t.evictions++; });
+            continue;
+        }
+        if (!budget_ok || busy) return false;  // wait: our own memory comes back later
+        // Within the budget, but the device does not have the memory and
+        // nothing of this server can release it: fail the build (the waiting
+        // requests get MPR_ENOMEM; a later request tries again).
+        Ladder &L = S.ladders[m];
+        L.m = m;
+        L.state = Ladder::FAILED;
+        L.fail_status = MPR_ENOMEM;
+        return true;
     }
     Ladder &L = S.ladders[m];
     L.m = m;
@@ -492,8 +525,12 @@ static void worker_main(Server *Sp)
         for (auto &kv : S.waiting) {
             Ladder &L = S.ladders[kv.first];
             if (L.state == Ladder::FAILED) {
+                // Report the failure to the requests that waited for this
+                // build, then forget it: a later request builds again (a
+                // failure may be transient, e.g. memory another process held).
                 for (auto &r : kv.second) complete(S, r, ROW_NONE, L.fail_status, S.now());
                 kv.second.clear();
+                L = Ladder();
                 continue;
             }
             if (L.state != Ladder::READY) continue;

@@ -260,7 +260,7 @@ mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hi
     return check_launch();
 }
 
-static std::atomic<int> g_sparse_arith{MPR_ARITH_F16};  // process-wide, set from any thread
+static std::atomic<int> g_sparse_arith{MPR_ARITH_U16};  // process-wide, set from any thread
 
 mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s)
 {

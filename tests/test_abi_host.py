@@ -89,7 +89,44 @@ def test_configs_describe_themselves(mpr):
         assert mpr.batch_config_info(c)["panel_rows"] in (32, 64, 128)
     with pytest.raises(mpr.MprError):
         mpr.set_tile_table([(100, 0), (50, 1)])  # not ascending
-    mpr.set_tile_table([(96, 3), (1024, 0), (1 << 62, 1)])
+    with pytest.raises(mpr.MprError):
+        mpr.set_tile_table([(100, 3), (1 << 62, 6)])  # two arithmetics in one table
+    from paper_2409_17658_amd import autotune
+
+    try:
+        mpr.set_tile_table([(96, 3), (1024, 0), (1 << 62, 1)])
+        mpr.set_tile_table([(96, 9), (1 << 62, 13)])
+        assert mpr.get_arith() == "u16"  # the default arithmetic
+        assert [mpr.gemm_pick_config(k, k, k) for k in (50, 500, 5000)] == [3, 0, 1]
+        with mpr.arith_scope("f16"):
+            assert [mpr.gemm_pick_config(k, k, k) for k in (50, 500, 5000)] == [9, 13, 13]
+        assert mpr.get_arith() == "u16"
+        with pytest.raises(ValueError):
+            mpr.set_arith("f32")
+    finally:
+        autotune.load_table()
+
+
+def test_batch_weights_install_and_reset(mpr):
+    """Weights of the batched-configuration model: one per configuration,
+    non-negative, each arithmetic keeping one; None restores the prior."""
+    cnt = mpr.batch_config_count()
+    prior = mpr.get_batch_weights()
+    try:
+        mpr.set_batch_weights(None)
+        base = mpr.get_batch_weights()
+        assert len(base) == cnt and all(w > 0 for w in base)
+        w = [0.0] * cnt
+        w[2], w[9] = 1.0, 0.5
+        mpr.set_batch_weights(w)
+        assert mpr.get_batch_weights() == w
+        for bad in ([1.0] * (cnt - 1), [0.0] * cnt, [-1.0] + [1.0] * (cnt - 1),
+                    [1.0] * 6 + [0.0] * (cnt - 6)):
+            with pytest.raises((mpr.MprError, ValueError)):
+                mpr.set_batch_weights(bad)
+        assert mpr.get_batch_weights() == w  # a refused table leaves the installed one
+    finally:
+        mpr.set_batch_weights(prior)
 
 
 def test_product_path_has_no_oracle_import():
@@ -144,14 +181,18 @@ def test_tile_table_loader_checks_configurations(mpr, tmp_path):
     from paper_2409_17658_amd import autotune
 
     cfgs = [mpr.gemm_config_info(c) for c in range(mpr.gemm_config_count())]
-    good = {"configs": cfgs, "measurements": [], "table": [[500, 3], [1 << 62, 1]]}
+    good = {"configs": cfgs, "measurements": [], "tables": {"u16": [[500, 3], [1 << 62, 1]],
+                                                             "f16": [[500, 9], [1 << 62, 7]]}}
     p = tmp_path / "t.json"
     p.write_text(json.dumps(good))
     try:
         assert autotune.load_table(str(p))
         assert mpr.gemm_pick_config(400, 400, 400) == 3 and mpr.gemm_pick_config(600, 600, 600) == 1
+        with mpr.arith_scope("f16"):
+            assert mpr.gemm_pick_config(400, 400, 400) == 9 and mpr.gemm_pick_config(600, 600, 600) == 7
         for bad in ({**good, "configs": cfgs[:-1]},
-                    {**good, "configs": [dict(cfgs[0], bm=cfgs[0]["bm"] * 2)] + cfgs[1:]}):
+                    {**good, "configs": [dict(cfgs[0], bm=cfgs[0]["bm"] * 2)] + cfgs[1:]},
+                    {"configs": cfgs, "measurements": [], "table": [[500, 3], [1 << 62, 1]]}):
             p.write_text(json.dumps(bad))
             assert not autotune.load_table(str(p))
             assert mpr.gemm_pick_config(400, 400, 400) == 3  # the installed table stays

@@ -179,16 +179,22 @@ def test_autotune_and_tile_table(mpr):
     assert len(ms) == mpr.gemm_config_count() and 0 <= best < len(ms)
     assert all(t > 0 for t in ms) and ms[best] == min(ms)
     prev = [mpr.gemm_pick_config(k, k, k) for k in (100, 300, 5000)]
+    X = synth.random_matrix(n, n, 61, 0, 40, 0.3)
+    Y = synth.random_matrix(n, n, 62, 0, 40, 0.3)
+    ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
     try:
-        mpr.set_tile_table([(250, best), (1 << 40, (best + 1) % len(ms))])
-        assert mpr.gemm_pick_config(n, n, n) == best
-        assert mpr.gemm_pick_config(300, 300, 300) == (best + 1) % len(ms)
-        X = synth.random_matrix(n, n, 61, 0, 40, 0.3)
-        Y = synth.random_matrix(n, n, 62, 0, 40, 0.3)
-        C = mpr.minplus_gemm(_dev(mpr, X), _dev(mpr, Y))
-        assert np.array_equal(_host(C), _u16(O.minplus(O.from_u16(X), O.from_u16(Y))))
+        for arith in ("u16", "f16"):
+            mine = [c for c in range(len(ms)) if mpr.gemm_config_info(c)["arith"] == arith]
+            fast = min(mine, key=lambda c: ms[c])
+            other = mine[(mine.index(fast) + 1) % len(mine)]
+            mpr.set_tile_table([(250, fast), (1 << 40, other)])
+            with mpr.arith_scope(arith):
+                assert mpr.gemm_pick_config(n, n, n) == fast
+                assert mpr.gemm_pick_config(300, 300, 300) == other
+                C = mpr.minplus_gemm(_dev(mpr, X), _dev(mpr, Y))
+                assert np.array_equal(_host(C), ref), arith
     finally:
-        mpr.init(0)  # reinstalls the persisted table
+        mpr.init(0)  # reinstalls the persisted tables
     assert [mpr.gemm_pick_config(k, k, k) for k in (100, 300, 5000)] == prev
 
 

@@ -45,16 +45,20 @@ def test_period_and_gamma_to_300(mpr, m):
         assert tr[k] == g["trace"][str(k)], k
 
 
+@pytest.mark.parametrize("arith", ["u16", "f16"])
 @pytest.mark.parametrize("m", [6, 7, 8])
-def test_chain_and_squaring_digests(mpr, m):
+def test_chain_and_squaring_digests(mpr, m, arith):
+    """Both arithmetic forms (the packed uint16 default and the f16 form)
+    give the oracle's canonical powers bit for bit."""
     g = load(m)
     A = mpr.build_transfer(m)
-    for k in (1, 2, 3, 21, 26, 64, 128, 299, 300):
-        for sched in (mpr.CHAIN, mpr.SQUARE):
-            if sched == mpr.CHAIN and k not in (1, 3, 26, 300):
-                continue
-            N, R = mpr.minplus_power(A, k, sched)
-            assert digest(N, R) == g["digest_sha256"][str(k)], (k, sched)
+    with mpr.arith_scope(arith):
+        for k in (1, 2, 3, 21, 26, 64, 128, 299, 300):
+            for sched in (mpr.CHAIN, mpr.SQUARE):
+                if sched == mpr.CHAIN and k not in (1, 3, 26, 300):
+                    continue
+                N, R = mpr.minplus_power(A, k, sched)
+                assert digest(N, R) == g["digest_sha256"][str(k)], (k, sched)
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7])
@@ -118,7 +122,7 @@ def test_sparse_chain_random_and_edge_blocks(mpr, arith):
             Nr, Rr = O.power_chain(O.from_u16(X), e)
             assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), n
     finally:
-        mpr.set_sparse_arith("f16")
+        mpr.set_sparse_arith("u16")
 
 
 def test_sparse_chain_u16_digests(mpr):
@@ -130,4 +134,4 @@ def test_sparse_chain_u16_digests(mpr):
             N, R = mpr.minplus_power(A, k, mpr.CHAIN_SPARSE)
             assert digest(N, R) == g["digest_sha256"][str(k)], k
     finally:
-        mpr.set_sparse_arith("f16")
+        mpr.set_sparse_arith("u16")

@@ -193,3 +193,58 @@ def test_batch_full_config4_sampled_rows(mpr):
     for (A, e, N, R) in chains[::8]:
         Ns, Rs = mpr.minplus_power(A, e, mpr.CHAIN, ws=ws)
         assert torch.equal(Ns.view(torch.int16), N.view(torch.int16)) and torch.equal(Rs, R)
+
+
+@pytest.mark.parametrize("arith", ["u16", "f16"])
+def test_batch_weights_route_the_plan(mpr, arith):
+    """An installed weight table (the form the batch autotuner persists)
+    steers the library's configuration model: with one configuration of the
+    process-wide arithmetic weighted far above the others the plan takes
+    it, and its results equal the oracle's."""
+    chains, mats = _small_batch(mpr)
+    cnt = mpr.batch_config_count()
+    prior = mpr.get_batch_weights()
+    mine = [c for c in range(cnt) if mpr.batch_config_info(c)["arith"] == arith]
+    ws = mpr.workspace(mpr.batch_workspace_size(chains))
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    try:
+        with mpr.arith_scope(arith):
+            for target in (mine[0], mine[2], mine[-1]):
+                print("batch weights", arith, target, flush=True)
+                w = [1e-3] * cnt
+                w[target] = 1.0
+                mpr.set_batch_weights(w)
+                mpr.batch_plan(chains, ws)
+                assert mpr.batch_plan_info(ws)[0] == target
+                for (_, _, N, R) in chains:
+                    N.view(torch.int16).fill_(7)
+                mpr.batch_launch(ws, st)
+                torch.cuda.synchronize()
+                assert int(st.item()) == 0
+                for (A, e, N, R), (X, _) in zip(chains, mats):
+                    Nr, Rr = O.power_chain(O.from_u16(X), e)
+                    assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
+    finally:
+        mpr.set_batch_weights(prior)
+
+
+def test_batch_autotuner_persists_and_installs(mpr, tmp_path):
+    """The batch autotuner times every batched configuration, persists the
+    relative throughputs (fastest = 1) and load_batch_table installs them;
+    the plan then follows the model with those weights."""
+    from paper_2409_17658_amd import autotune
+
+    prior = mpr.get_batch_weights()
+    p = tmp_path / "batch.json"
+    try:
+        out = autotune.tune_batch(chains=16, n=256, e=3, reps=1, path=str(p))
+        w = out["weights"]
+        assert len(w) == mpr.batch_config_count() and max(w) == 1.0 and min(w) > 0
+        mpr.set_batch_weights(None)
+        assert autotune.load_batch_table(str(p))
+        assert mpr.get_batch_weights() == pytest.approx(w)
+        bad = dict(out, configs=out["configs"][:-1])
+        p.write_text(__import__("json").dumps(bad))
+        assert not autotune.load_batch_table(str(p))
+    finally:
+        mpr.set_batch_weights(prior)

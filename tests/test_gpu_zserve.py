@@ -182,3 +182,59 @@ def test_server_busy_poll(serve):
         res = serve.run_open_loop(S, qs, timeout_s=120)
     for (_, m, n), r in zip(qs, res):
         assert r["status"] == 0 and r["gamma"] == oracle_gamma(m, n), (m, n)
+
+
+def test_warm_queries_overlap_a_cold_build(serve):
+    """Continuous batching with overlap: an m = 9 request arrives first and
+    waits seconds for its ladder (built on the build stream); warm requests
+    for m = 3..8 submitted after it are all answered before it, each equal
+    to the stored gamma_R table (m = 9: Section 4.3's closed form)."""
+    rng = np.random.default_rng(23)
+    warm = [(int(m), int(n)) for m, n in zip(rng.integers(3, 9, 150), rng.integers(3, 1001, 150))]
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=4, hbm_budget_bytes=200 << 30) as S:
+        for m in range(3, 9):
+            assert S.query(m, 1000)["status"] == 0  # ladders of m = 3..8 resident
+        builds0 = S.stats()["builds"]
+        S.submit(9, 997, 10 ** 6)
+        got, t_end = {}, time.monotonic() + 300
+        for k, (m, n) in enumerate(warm):
+            S.submit(m, n, k)
+            time.sleep(0.004)
+        while 10 ** 6 not in got and time.monotonic() < t_end:
+            for r in S.poll(20):
+                got[r["tag"]] = r
+        st = S.stats()
+    big = got[10 ** 6]
+    assert big["status"] == 0 and big["cold"] == 1 and big["gamma"] == 4 * 997 + 2
+    assert st["builds"] == builds0 + 1
+    assert len(got) == len(warm) + 1  # every warm answer came before the cold one
+    for k, (m, n) in enumerate(warm):
+        r = got[k]
+        assert r["status"] == 0 and r["cold"] == 0 and r["gamma"] == golden_gamma(m, n), (m, n)
+        assert r["t_done"] < big["t_done"] and r["t_submit"] > big["t_submit"]
+
+
+def test_build_refused_without_free_memory_then_retried(serve):
+    """Admission is by the device's free memory as well as the byte budget:
+    with almost all of the device's memory held elsewhere (a host-side
+    allocation, no fault involved) a ladder that fits the budget is refused
+    with MPR_ENOMEM (the idle ladder is evicted first); the failure is not
+    kept, so once the memory is back the next request builds and answers."""
+    import torch
+
+    with serve.Server(baby=8, max_n=40, max_batch=8, slots=1, hbm_budget_bytes=8 << 30) as S:
+        assert S.query(3, 10)["status"] == 0
+        free, _ = torch.cuda.mem_get_info()
+        hog = torch.empty(max(0, free - (64 << 20)), dtype=torch.uint8, device="cuda")
+        try:
+            r1 = S.query(4, 20)
+        finally:
+            del hog
+            torch.cuda.empty_cache()
+        r2 = S.query(4, 21)
+        r3 = S.query(3, 11)
+        st = S.stats()
+    assert r1["status"] == 2  # MPR_ENOMEM
+    assert r2["status"] == 0 and r2["gamma"] == oracle_gamma(4, 21)
+    assert r3["status"] == 0 and r3["gamma"] == oracle_gamma(3, 11)
+    assert st["evictions"] >= 1

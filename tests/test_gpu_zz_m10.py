@@ -2,11 +2,15 @@
 such matrices): gamma_R(P_10 x C_n) by the transfer method (compressed-K
 chain steps, a ring of 8 resident powers) against the oracle's row DP
 (n <= 9, stored golden written by an oracle-only script), Remark 13 and
-Theorem 11."""
+Theorem 11; and sampled rows of the powers A^k themselves (k = 11, 22, 30)
+against the oracle's chain over the rows of A (A held by its arcs), which
+pins gamma_R(P_10 x C_n) beyond n <= 9 and n = 0 (mod 5)."""
 import json
 import os
 
+import numpy as np
 import pytest
+import torch
 
 pytestmark = pytest.mark.gpu
 
@@ -31,3 +35,30 @@ def test_m10_gamma(paper_values):
         assert mpr.gamma_from_period(mu, lam, c, tr, n) == 22 * n // 5
     for n in range(10, 2001):
         assert mpr.gamma_from_period(mu, lam, c, tr, n) >= -(-22 * n // 5)
+
+
+def test_m10_power_rows_match_oracle():
+    """Eight rows of A^11, A^22 and A^30 (m = 10, the compressed-K chain in
+    the library's default arithmetic) equal the oracle's row chain bit for
+    bit: canonical entries and offsets."""
+    import oracle as O
+    import paper_2409_17658_amd as mpr
+
+    mpr.init(0)
+    m, ks = 10, (11, 22, 30)
+    n = mpr.transfer_size(m)
+    rows = [0, 1, 17, 12345, 32384, 50000, n - 2, n - 1]
+    want = {}
+    O.chain_rows_sparse(O.transfer_rows(m, rows), O.transfer_arcs(m), max(ks),
+                        on_step=lambda k, N, R: want.__setitem__(k, (O.to_u16(N), R.copy())) if k in ks else None)
+    print("m10 oracle rows done", flush=True)
+    A = mpr.build_transfer(m)
+    ws = mpr.workspace(mpr.power_workspace_size(n, max(ks), mpr.CHAIN_SPARSE))
+    N = mpr.alloc_matrix(n, n)
+    R = torch.empty(n, dtype=torch.int64, device="cuda")
+    idx = torch.as_tensor(rows, device="cuda")
+    for k in ks:
+        mpr.minplus_power(A, k, mpr.CHAIN_SPARSE, N, R, ws, check=True)
+        print("m10 power", k, flush=True)
+        assert np.array_equal(N[idx].cpu().numpy(), want[k][0]), k
+        assert np.array_equal(R[idx].cpu().numpy(), want[k][1]), k

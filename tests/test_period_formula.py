@@ -68,3 +68,18 @@ def test_bad_arguments(mpr):
         mpr.gamma_from_period(8, 5, 1, tr, 20)  # mu + lam - 1 > kmax
     with pytest.raises(mpr.MprError):
         mpr.gamma_from_period(0, 5, 1, tr, 20)
+
+
+def test_empty_residue_class_stays_empty(mpr):
+    """A directed 2-cycle with arc weights 1: closed walks exist only for
+    even lengths, so the trace of A^k is +infinity (MPR_ROW_NONE) for odd k
+    and k for even k; A^(k+2) = 2 (x) A^k from k = 1.  The extension and the
+    closed form keep the odd class empty instead of adding to infinity."""
+    mu, lam, c = 1, 2, 2
+    none = mpr.ROW_NONE
+    tr = np.array([none, none, 2], dtype=np.int64)  # traces of A^1, A^2 (index 0 unused)
+    for n in range(1, 60):
+        want = n if n % 2 == 0 else none
+        assert mpr.gamma_from_period(mu, lam, c, tr, n) == want, n
+    numer = mpr.period_formula(mu, lam, c, tr)
+    assert numer[1] == none and numer[0] == 0  # gamma(n) = (2n + 0) / 2 for even n
