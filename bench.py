@@ -443,7 +443,9 @@ def bench_m10(args, mpr, torch):
     torch.cuda.synchronize()
     print("m10: transfer matrix built, %d states" % n, file=sys.stderr, flush=True)
     flags = mpr.PERIOD_SPARSE if args.m10_sparse else 0
-    ws = mpr.workspace(mpr.period_workspace_size(n, 8, flags))
+    plan_b = mpr.sparse_plan_bytes(A) if args.m10_sparse else 0  # the plan sized for this A
+    ws_b = mpr.period_workspace_size(n, 8, 0) + plan_b
+    ws = mpr.workspace(ws_b)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mu, lam, c, tr = mpr.find_period(A, kmax, traces=True, ws=ws, sparse=bool(args.m10_sparse))
@@ -464,6 +466,9 @@ def bench_m10(args, mpr, torch):
            "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n,
                       "chain_step": "compressed-K (sparse A)" if args.m10_sparse else "dense"},
            "period": [mu, lam, c], "seconds": round(t, 1), "gamma": gam,
+           "workspace_gb": round(ws_b / 1e9, 2), "plan_gb": round(plan_b / 1e9, 3),
+           "plan_worst_case_gb": round((mpr.period_workspace_size(n, 8, flags) -
+                                        mpr.period_workspace_size(n, 8, 0)) / 1e9, 2),
            "to_period_s": round(t_ext, 2),
            "extended_traces_same": (mue, lame, ce) == (mu, lam, c) and bool(np.array_equal(tre, tr))}
     if mu is not None:
@@ -599,6 +604,13 @@ def _timed(torch, fn):
     return r, time.perf_counter() - t0
 
 
+def _rows(torch, t, rows):
+    """Rows of a device uint16 matrix on the host (through an int16 view:
+    torch does not index uint16 device tensors)."""
+    idx = torch.as_tensor(np.asarray(rows), device=t.device)
+    return t.view(torch.int16)[idx].cpu().numpy().view(np.uint16)
+
+
 def _same(torch, a, b):
     return bool(torch.equal(a[0].view(torch.int16), b[0].view(torch.int16)) and torch.equal(a[1], b[1]))
 
@@ -670,8 +682,7 @@ def leg_config2(mpr, torch, args):
     Nr, Rr = O.chain_rows(O.from_u16(X), rows, e)
     t_cpu = time.perf_counter() - t0
     (Nu, Ru), t_chain = out["u16"]
-    idx = torch.as_tensor(rows, device="cuda")
-    ok = np.array_equal(Nu[idx].cpu().numpy(), O.to_u16(Nr)) and np.array_equal(Ru[idx].cpu().numpy(), Rr)
+    ok = np.array_equal(_rows(torch, Nu, rows), O.to_u16(Nr)) and np.array_equal(Ru.cpu().numpy()[rows], Rr)
     return {"workload": "N=8192 uint16 (seed 3, U[0,15], 30% inf): one product, A^64 by the chain",
             "value": round(63 * pairs / t_chain / 1e9, 1), "unit": "G pairs/s", "dtype": "uint16",
             "chain_s": round(t_chain, 3), "single_product_ms": round(t_single * 1e3, 3),
@@ -726,9 +737,8 @@ def leg_config3(mpr, torch, goldens, args):
             oracle_ok = True
         t_cpu = time.perf_counter() - t0
         (Nc, Rc), t_chain = res["chain"]
-        idx = torch.as_tensor(rows, device="cuda")
-        oracle_ok = oracle_ok and np.array_equal(Nc[idx].cpu().numpy(), O.to_u16(Nr)) and \
-            np.array_equal(Rc[idx].cpu().numpy(), Rr)
+        oracle_ok = oracle_ok and np.array_equal(_rows(torch, Nc, rows), O.to_u16(Nr)) and \
+            np.array_equal(Rc.cpu().numpy()[rows], Rr)
         pairs = 299 * float(n) ** 3
         tot_pairs += pairs
         tot_t += t_chain
@@ -803,8 +813,7 @@ def leg_config4(mpr, torch, args):
         rows = np.sort(np.random.default_rng(i).choice(n, args.config4_rows, replace=False))
         Nr, Rr = O.chain_rows(O.from_u16(mats[i]), rows, e)
         N, R = forms["u16"][2][i]
-        idx = torch.as_tensor(rows, device="cuda")
-        ok = ok and np.array_equal(N[idx].cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R[idx].cpu().numpy(), Rr)
+        ok = ok and np.array_equal(_rows(torch, N, rows), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy()[rows], Rr)
         sampled += len(rows) * (e - 1) * float(n) * n
     t_cpu = time.perf_counter() - t0
     cfg, t_batch, _ = forms["u16"]

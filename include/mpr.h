@@ -191,10 +191,27 @@ mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *
  * have a finite entry in J (C[:, J] = N[:, L_J] (x) A[L_J, J], the same
  * product; worth it when A is sparse, as transfer matrices are).  All three
  * give identical bits.  N_out is n x n
- * (ldo), R_out has n entries. */
+ * (ldo), R_out has n entries.  For MPR_CHAIN_SPARSE a workspace smaller
+ * than mpr_power_workspace_size gives the plan what is left after the
+ * chain buffer (see mpr_sparse_plan_bytes); d_status must then be given. */
 mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t lda, int64_t e,
                              int schedule, uint16_t *N_out, int64_t ldo, int64_t *R_out,
                              void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
+
+/* Bytes of the compressed-K plan of the n x n device matrix A (row stride
+ * lda): for every block J of 64 columns, the rows of A with a finite entry
+ * in J (rounded up to 32 per block) and their packed entries -- a few per
+ * cent of the worst case that mpr_power_workspace_size and
+ * mpr_period_workspace_size_ex assume (a dense A) for transfer matrices.
+ * A workspace of mpr_power_workspace_size(n, e, MPR_CHAIN) + this many bytes
+ * serves mpr_minplus_power(..., MPR_CHAIN_SPARSE) on this A (a d_status is
+ * then required: a plan that does not fit its share sets MPR_ENOMEM there
+ * and the call computes nothing), and mpr_period_workspace_size_ex(n,
+ * slots, 0) + this many bytes serves mpr_find_period_ex with
+ * MPR_PERIOD_SPARSE (which sizes the plan itself and gives the ring every
+ * other byte).  SYNCHRONOUS on stream; sizing only: it allocates and frees a
+ * device temporary of about 16 (n / 64 + 2) bytes. */
+mpr_status mpr_sparse_plan_bytes(const uint16_t *A, int64_t n, int64_t lda, size_t *bytes_host, mpr_stream stream);
 
 /* Corollary 7: *d_gamma = min_i (R[i] + N[i][i]) over rows with a finite
  * diagonal entry (MPR_ROW_NONE if there is none).  For N, R = A^n this is
@@ -229,7 +246,9 @@ mpr_status mpr_trace_of_product_t(const uint16_t *X, const int64_t *RX,
 
 /* Workspace bytes to keep `slots` powers of an n x n matrix resident
  * (slots >= 2).  The period search keeps the last `slots` powers in a ring,
- * so it can confirm a period lam only when lam < slots; mu is unbounded. */
+ * so it can confirm a period lam only when lam < slots; mu is unbounded.
+ * The ring takes every byte of the workspace past the fixed part (and, with
+ * MPR_PERIOD_SPARSE, past the plan, sized for the given A). */
 mpr_status mpr_period_workspace_size(int64_t n, int64_t slots, size_t *bytes_host);
 
 /* Least (mu, lam, c) with A^(mu+lam) = c (x) A^mu, searching the chain
@@ -269,7 +288,9 @@ mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t 
 
 /* mpr_find_period with flags: MPR_PERIOD_SPARSE runs the chain steps as
  * MPR_CHAIN_SPARSE does (identical results).  The workspace must then be
- * sized by mpr_period_workspace_size_ex with the same flags.
+ * sized by mpr_period_workspace_size_ex with the same flags (the worst
+ * case), or by mpr_period_workspace_size_ex(n, slots, 0) plus
+ * mpr_sparse_plan_bytes of this A.
  * MPR_PERIOD_EXTEND stops at the power that confirms the period (k = mu +
  * lambda, as Algorithm 2 does) instead of computing every power to kmax,
  * and fills traces_host[k] for mu + lambda < k <= kmax from the relation

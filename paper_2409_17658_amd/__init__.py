@@ -90,6 +90,7 @@ _SIGS = {
                                    _P, _SZ, _P, _P]),
     "mpr_power_workspace_size": (_I, [_I64, _I64, _I, _P]),
     "mpr_minplus_power": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _SZ, _P, _P]),
+    "mpr_sparse_plan_bytes": (_I, [_P, _I64, _I64, _P, _P]),
     "mpr_trace_min": (_I, [_P, _I64, _I64, _P, _P, _P]),
     "mpr_trace_of_product": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
     "mpr_trace_of_product_t": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
@@ -333,14 +334,25 @@ def minplus_power(A, e: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=N
         N_out = alloc_matrix(n, n, A.device)
     if R_out is None:
         R_out = torch.empty(n, dtype=torch.int64, device=A.device)
-    if ws is None:
-        ws = workspace(power_workspace_size(n, e, schedule), A.device)
     st = d_status if d_status is not None else (_status_tensor(A.device) if check else None)
+    if ws is None:
+        if schedule == CHAIN_SPARSE and st is not None and e >= 2:  # the plan sized for this A
+            ws = workspace(power_workspace_size(n, e, CHAIN) + 256 + sparse_plan_bytes(A, stream), A.device)
+        else:
+            ws = workspace(power_workspace_size(n, e, schedule), A.device)
     _ok(lib().mpr_minplus_power(_ptr(A), n, _ld(A), e, schedule, _ptr(N_out), _ld(N_out), _vptr(R_out, n),
                                 _ptr(ws), ws.numel(), _ptr(st), _stream(stream)), "mpr_minplus_power")
     if check and d_status is None:
         check_status(st)
     return N_out, R_out
+
+
+def sparse_plan_bytes(A, stream=None) -> int:
+    """Bytes of the compressed-K plan of A (synchronous)."""
+    nb = ctypes.c_size_t()
+    _ok(lib().mpr_sparse_plan_bytes(_ptr(A), A.shape[0], _ld(A), ctypes.byref(nb), _stream(stream)),
+        "mpr_sparse_plan_bytes")
+    return nb.value
 
 
 def trace_min(N, R, out=None, stream=None):
@@ -387,8 +399,9 @@ def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, str
     from the period (exact)."""
     n = A.shape[0]
     flags = (PERIOD_SPARSE if sparse else 0) | (PERIOD_EXTEND if extend else 0)
-    if ws is None:
-        ws = workspace(period_workspace_size(n, slots, flags), A.device)
+    if ws is None:  # with sparse=True the plan is sized for this A
+        ws = workspace(period_workspace_size(n, slots, 0) + (sparse_plan_bytes(A, stream) if sparse else 0),
+                       A.device)
     mu, lam, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     tr = np.zeros(kmax + 1, dtype=np.int64) if traces else None
     st = lib().mpr_find_period_ex(_ptr(A), n, _ld(A), kmax, flags, ctypes.byref(mu), ctypes.byref(lam),

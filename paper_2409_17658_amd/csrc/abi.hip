@@ -108,12 +108,17 @@ static size_t gemm_norm_ws(int64_t K, int64_t N, int64_t *ldp_out)
 struct PowerWs {
     u16 *P, *acc, *Bp, *C;
     int64_t *RP, *Racc, *RC, *s;
-    void *plan;  // compressed-K plan of A (MPR_CHAIN_SPARSE)
+    void *plan;         // compressed-K plan of A (MPR_CHAIN_SPARSE)
+    size_t plan_bytes;  // its share of the workspace
+    bool plan_full;     // sized for the worst case (any A fits)
     int64_t ld;
     size_t bytes;
 };
 
-static PowerWs carve_power(void *ws, int64_t n, int schedule)
+// Workspace layout of mpr_minplus_power.  The compressed-K plan takes the
+// rest of a workspace of ws_bytes, up to its worst case; ws_bytes = 0 (or
+// more than needed) sizes it for the worst case.
+static PowerWs carve_power(void *ws, int64_t n, int schedule, size_t ws_bytes = 0)
 {
     PowerWs w{};
     w.ld = round_up(n > 0 ? n : 1, 8);
@@ -128,7 +133,12 @@ static PowerWs carve_power(void *ws, int64_t n, int schedule)
         w.RC = c.take<int64_t>((size_t)n);
         w.s = c.take<int64_t>(1);
     }
-    if (schedule == MPR_CHAIN_SPARSE) w.plan = c.take<char>(sparse_plan_bytes(n));
+    if (schedule == MPR_CHAIN_SPARSE) {
+        const size_t at = (size_t)round_up((int64_t)c.used, 256), worst = sparse_plan_bytes(n);
+        w.plan_bytes = (ws_bytes > at + 256 && ws_bytes - at - 256 < worst) ? ws_bytes - at - 256 : worst;
+        w.plan_full = w.plan_bytes == worst;
+        w.plan = c.take<char>(w.plan_bytes);
+    }
     w.bytes = c.used + 256;
     return w;
 }
@@ -142,10 +152,10 @@ static mpr_status power_chain(const u16 *A, int64_t n, int64_t lda, int64_t e, u
     int b = (int)((e - 1) & 1);
     mpr_status r = copy_launch(A, lda, buf[b], ld[b], n, n, s);
     if (r == MPR_OK) r = normalise_launch(n, n, buf[b], ld[b], nullptr, nullptr, R_out, st, nullptr, s);
-    if (r == MPR_OK && sparse && e >= 2) r = sparse_plan_launch(A, n, lda, w.plan, s);
+    if (r == MPR_OK && sparse && e >= 2) r = sparse_plan_launch(A, n, lda, w.plan, w.plan_bytes, st, s);
     for (int64_t k = 2; k <= e && r == MPR_OK; k++) {
         const int nb = b ^ 1;
-        r = sparse ? sparse_step_launch(buf[b], ld[b], n, w.plan, buf[nb], ld[nb], s)
+        r = sparse ? sparse_step_launch(buf[b], ld[b], n, w.plan, w.plan_bytes, buf[nb], ld[nb], s)
                    : gemm_launch(-1, n, n, n, buf[b], ld[b], A, lda, buf[nb], ld[nb], s);
         if (r == MPR_OK) r = normalise_launch(n, n, buf[nb], ld[nb], R_out, nullptr, R_out, st, nullptr, s);
         b = nb;
@@ -191,6 +201,7 @@ static mpr_status power_square(const u16 *A, int64_t n, int64_t lda, int64_t e, 
 struct PeriodWs {
     uint64_t *row_hash;
     void *plan;
+    size_t plan_bytes;
     int64_t *scal;  // [0] hash, [1] trace, [2] status (int32 in low half), [3..5] compare
     int64_t slots;
     int64_t ld;
@@ -200,14 +211,21 @@ struct PeriodWs {
     size_t fixed;
 };
 
-static PeriodWs carve_period(void *ws, int64_t n, size_t ws_bytes, int64_t slots_req, int flags)
+// Workspace layout of the period search: the per-row hashes and scalars,
+// then (MPR_PERIOD_SPARSE) the compressed-K plan of plan_bytes (the worst
+// case when 0), then the ring of power slots.
+static PeriodWs carve_period(void *ws, int64_t n, size_t ws_bytes, int64_t slots_req, int flags,
+                             size_t plan_bytes = 0)
 {
     PeriodWs w{};
     w.ld = round_up(n > 0 ? n : 1, 8);
     Carver c(ws);
     w.row_hash = c.take<uint64_t>((size_t)n);
     w.scal = c.take<int64_t>(8);
-    w.plan = (flags & MPR_PERIOD_SPARSE) ? (void *)c.take<char>(sparse_plan_bytes(n)) : nullptr;
+    if (flags & MPR_PERIOD_SPARSE) {
+        w.plan_bytes = plan_bytes ? plan_bytes : sparse_plan_bytes(n);
+        w.plan = (void *)c.take<char>(w.plan_bytes);
+    }
     w.fixed = (size_t)round_up((int64_t)c.used, 256);
     w.slot_elems = (size_t)(n * w.ld);
     w.slot_bytes = (size_t)round_up((int64_t)(w.slot_elems * 2), 256) + (size_t)round_up(n * 8, 256);
@@ -376,14 +394,37 @@ extern "C" mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t ld
     if (n && (!A || !N_out || !R_out)) return MPR_EINVAL;
     if (!ld_ok(lda, n) || !ld_ok(ldo, n)) return MPR_EINVAL;
     if (n == 0) return MPR_OK;
-    PowerWs w = carve_power(ws, n, schedule);
+    PowerWs w = carve_power(ws, n, schedule, ws_bytes);
     if (!ws || ws_bytes < w.bytes) return MPR_ENOMEM;
+    if (schedule == MPR_CHAIN_SPARSE && !w.plan_full) {
+        // A plan smaller than the worst case: too small even for the counts,
+        // or no status word to report a plan that does not fit.
+        if (w.plan_bytes < sparse_plan_bytes_rows(n, 0)) return MPR_ENOMEM;
+        if (!d_status) return MPR_EINVAL;
+    }
     mpr_status r = ensure_init();
     if (r != MPR_OK) return r;
     hipStream_t s = as_stream(stream);
     if ((r = validate_launch(A, n, n, lda, d_status, s)) != MPR_OK) return r;
     if (schedule == MPR_SQUARE) return power_square(A, n, lda, e, N_out, ldo, R_out, w, d_status, s);
     return power_chain(A, n, lda, e, N_out, ldo, R_out, w, d_status, s, schedule == MPR_CHAIN_SPARSE);
+}
+
+extern "C" mpr_status mpr_sparse_plan_bytes(const uint16_t *A, int64_t n, int64_t lda, size_t *bytes_host,
+                                            mpr_stream stream)
+{
+    if (n < 1 || !A || !bytes_host || !ld_ok(lda, n)) return MPR_EINVAL;
+    mpr_status r = ensure_init();
+    if (r != MPR_OK) return r;
+    hipStream_t s = as_stream(stream);
+    const size_t tmp_bytes = sparse_plan_bytes_rows(n, 0);
+    void *tmp = nullptr;
+    if (hipMallocAsync(&tmp, tmp_bytes, s) != hipSuccess) return MPR_ENOMEM;
+    int64_t rows = 0;
+    r = sparse_plan_rows(A, n, lda, tmp, s, &rows);
+    if (hipFreeAsync(tmp, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) r = r != MPR_OK ? r : MPR_EHIP;
+    if (r == MPR_OK) *bytes_host = sparse_plan_bytes_rows(n, rows);
+    return r;
 }
 
 extern "C" mpr_status mpr_trace_min(const uint16_t *N, int64_t n, int64_t ld, const int64_t *R, int64_t *d_gamma,
@@ -435,15 +476,26 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
     if (n < 1 || kmax < 1 || !A || !mu_host || !lam_host || !c_host || !ld_ok(lda, n)) return MPR_EINVAL;
     if (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND)) return MPR_EINVAL;
     const bool sparse = (flags & MPR_PERIOD_SPARSE) != 0;
-    PeriodWs w = carve_period(ws, n, ws_bytes, 0, flags);
-    if (!ws || w.slots < 2) return MPR_ENOMEM;
+    if (!ws) return MPR_ENOMEM;
     mpr_status r = ensure_init();
     if (r != MPR_OK) return r;
     hipStream_t s = as_stream(stream);
+    // The compressed-K plan is sized for this A (its rows are counted first,
+    // one host round trip), so the ring gets every byte the plan does not use.
+    size_t plan_bytes = 0;
+    if (sparse) {
+        PeriodWs probe = carve_period(ws, n, ws_bytes, 0, 0);
+        if (ws_bytes < probe.fixed + sparse_plan_bytes_rows(n, 0)) return MPR_ENOMEM;
+        int64_t rows = 0;
+        if ((r = sparse_plan_rows(A, n, lda, (char *)ws + probe.fixed, s, &rows)) != MPR_OK) return r;
+        plan_bytes = sparse_plan_bytes_rows(n, rows);
+    }
+    PeriodWs w = carve_period(ws, n, ws_bytes, 0, flags, plan_bytes);
+    if (w.slots < 2) return MPR_ENOMEM;
     int32_t *st = (int32_t *)&w.scal[2];
     if ((r = fill_i32_launch(st, 2, 0, s)) != MPR_OK) return r;
     if ((r = validate_launch(A, n, n, lda, st, s)) != MPR_OK) return r;
-    if (sparse && (r = sparse_plan_launch(A, n, lda, w.plan, s)) != MPR_OK) return r;
+    if (sparse && (r = sparse_plan_launch(A, n, lda, w.plan, w.plan_bytes, st, s)) != MPR_OK) return r;
     if (traces_host) traces_host[0] = MPR_ROW_NONE;
 
     // Power k lives in slot (k - 1) % slots (a ring), so a repeat of the class
@@ -460,7 +512,7 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
             r = copy_launch(A, lda, Nk, w.ld, n, n, s);
             if (r == MPR_OK) r = normalise_launch(n, n, Nk, w.ld, nullptr, nullptr, Rk, st, w.row_hash, s);
         } else {
-            r = sparse ? sparse_step_launch(slot_N(w, prev_slot), w.ld, n, w.plan, Nk, w.ld, s)
+            r = sparse ? sparse_step_launch(slot_N(w, prev_slot), w.ld, n, w.plan, w.plan_bytes, Nk, w.ld, s)
                        : gemm_launch(-1, n, n, n, slot_N(w, prev_slot), w.ld, A, lda, Nk, w.ld, s);
             if (r == MPR_OK)
                 r = normalise_launch(n, n, Nk, w.ld, slot_R(w, prev_slot), nullptr, Rk, st, w.row_hash, s);
@@ -472,7 +524,7 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
         if (hipMemcpyAsync(host, w.scal, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return MPR_EHIP;
-        if ((int32_t)(host[2] & 0xFFFFFFFF) != 0) return MPR_EOVERFLOW;
+        if ((int32_t)(host[2] & 0xFFFFFFFF) != 0) return (mpr_status)(int32_t)(host[2] & 0xFFFFFFFF);
         if (traces_host) traces_host[k] = host[1];
         prev_slot = slot;
         if (!found) {

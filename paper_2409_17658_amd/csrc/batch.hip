@@ -138,10 +138,28 @@ struct BatchWaves {
     static constexpr int value = (T::TM * T::TN <= 32) ? 4 : 2;
 };
 
+// Largest value a panel may carry into the next product without being
+// normalised first.  Row i of (s (+) N) (x) A is s_i (+) the row of N (x) A
+// (the scalar rule of Section 3), so a panel can skip the per-step
+// normalisation and keep its row offsets inside its values for as long as
+// they stay small: in uint16 every finite input <= MPR_FMAX is exact; in the
+// f16 form inputs up to 1023 keep the sums with A's small entries inside
+// the exact range (larger ones would only send tiles to the uint16 redo).
+// The row minima are still taken every step, and the canonical form is
+// written at the last step, so the results are the same bits.
+template <bool H>
+struct LazyMax {
+    static constexpr uint32_t value = H ? 0x3FFu : FMAX16;
+};
+
 // One panel: all e - 1 chain steps of rows [row0, row0 + BM) of one chain.
+// A step computes the raw product of the panel with A column tile by column
+// tile, keeping each row's least value and largest finite value in LDS; the
+// panel is normalised in place (offsets into R) only when a row's largest
+// value passes LazyMax, and at the last step.
 template <class T, bool H>
 __device__ __forceinline__ void batch_item(const DevChain *__restrict__ chains, const BatchItem item, u16 *lds,
-                                           uint32_t *rmin, int32_t *st)
+                                           uint32_t *rmin, uint32_t *rmax, int32_t *st)
 {
     const DevChain c = chains[item.inst];
     const int64_t n = c.n, r0 = item.row0;
@@ -163,7 +181,10 @@ __device__ __forceinline__ void batch_item(const DevChain *__restrict__ chains, 
     for (int64_t k = 2; k <= c.e; k++) {
         __syncthreads();
         const int nb = b ^ 1;
-        for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) rmin[rr] = 0xFFFFu;
+        for (int rr = threadIdx.x; rr < T::BM; rr += T::NT) {
+            rmin[rr] = 0xFFFFu;
+            rmax[rr] = 0u;
+        }
         // (visibility of rmin is covered by the barriers inside the tile loop)
         // 32-bit offsets: n <= 32768 and leading dimensions <= 65528.
         const gu16 *Lp = glob(buf[b]) + r0 * ld[b];
@@ -223,22 +244,35 @@ __device__ __forceinline__ void batch_item(const DevChain *__restrict__ chains, 
             }
 #pragma unroll
             for (int r = 0; r < T::TM; r++) {
-                uint32_t m = 0xFFFFu;
+                // Least value, and largest finite value + 1 (infinity wraps to
+                // 0), two columns per packed instruction; columns past the end
+                // of the chain are infinite (A was read as infinity there).
+                u16x2 mn = {0xFFFF, 0xFFFF}, mx = {0, 0};
 #pragma unroll
                 for (int q = 0; q < T::NACC; q++) {
-                    const uint32_t w = as_u32(acc.v[r][q]);
-                    const int col = tile_col<T>(q >> 2) + 2 * (q & 3);
-                    if (n0 + col < n) m = min(m, w & 0xFFFFu);
-                    if (n0 + col + 1 < n) m = min(m, w >> 16);
+                    mn = min2(mn, acc.v[r][q]);
+                    mx = __builtin_elementwise_max(mx, acc.v[r][q] + (u16x2){1, 1});
                 }
+                uint32_t m = min((uint32_t)mn.x, (uint32_t)mn.y), x = max((uint32_t)mx.x, (uint32_t)mx.y);
                 // lanes tx = 0..TX-1 of one row group are consecutive
 #pragma unroll
-                for (int off = 1; off < T::TX; off <<= 1) m = min(m, (uint32_t)__shfl_xor(m, off, 64));
-                if (threadIdx.x % T::TX == 0) atomicMin(&rmin[tile_row<T>(r)], m);
+                for (int off = 1; off < T::TX; off <<= 1) {
+                    m = min(m, (uint32_t)__shfl_xor(m, off, 64));
+                    x = max(x, (uint32_t)__shfl_xor(x, off, 64));
+                }
+                if (threadIdx.x % T::TX == 0) {
+                    atomicMin(&rmin[tile_row<T>(r)], m);
+                    atomicMax(&rmax[tile_row<T>(r)], x);
+                }
             }
         }
         __syncthreads();
-        panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, vec, st);
+        // Rows past the chain's end hold only infinity (x = 0), so they never
+        // ask for a normalisation.
+        bool wide = false;
+        for (int rr = threadIdx.x; rr < rows; rr += T::NT) wide |= rmax[rr] > LazyMax<H>::value + 1u;
+        if (__syncthreads_or(wide) || k == c.e)
+            panel_normalise<T::NT>(buf[nb], ld[nb], buf[nb], ld[nb], r0, rows, n, rmin, c.R_out, false, vec, st);
         b = nb;
     }
 }
@@ -249,7 +283,7 @@ void batch_kernel(const DevChain *__restrict__ chains, const BatchItem *__restri
                   int *counter, int persistent, int32_t *st)
 {
     __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
-    __shared__ uint32_t rmin[T::BM];
+    __shared__ uint32_t rmin[T::BM], rmax[T::BM];
     __shared__ int next;
     // Each workgroup takes the next item with one atomic add, so the k-th item
     // taken is the k-th longest.  One workgroup per item by default; in the
@@ -261,9 +295,9 @@ void batch_kernel(const DevChain *__restrict__ chains, const BatchItem *__restri
         const int it = next;
         __syncthreads();  // every thread has read `next` before it changes
         if (it >= n_items) return;  // block-uniform
-        batch_item<T, H>(chains, items[it], lds, rmin, st);
+        batch_item<T, H>(chains, items[it], lds, rmin, rmax, st);
         if (!persistent) return;
-        __syncthreads();  // the next item reuses lds and rmin
+        __syncthreads();  // the next item reuses lds, rmin and rmax
     }
 }
 

@@ -133,9 +133,13 @@ int pick_config_arith(int arith, int64_t M, int64_t N, int64_t K);
 int current_arith();
 
 // sparse.hip
-size_t sparse_plan_bytes(int64_t n);
-mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hipStream_t s);
-mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s);
+size_t sparse_plan_bytes(int64_t n);                      // worst case (dense A)
+size_t sparse_plan_bytes_rows(int64_t n, int64_t rows);   // a plan of `rows` rows
+mpr_status sparse_plan_rows(const u16 *A, int64_t n, int64_t lda, void *ws, hipStream_t s, int64_t *rows);
+mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, size_t bytes, int32_t *st,
+                              hipStream_t s);
+mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, size_t bytes, u16 *C, int64_t ldc,
+                              hipStream_t s);
 
 // rowops.hip
 mpr_status validate_launch(const u16 *X, int64_t rows, int64_t cols, int64_t ld, int32_t *st, hipStream_t s);

@@ -246,7 +246,8 @@ static mpr_status start_build(Server &S, Ladder &L)
     int64_t *scal = (int64_t *)p;  // [0] s of the fold, [1..B] traces, the status word, the byte-copy flag
     p += round_up((int64_t)(B + 8) * 8, 256);
     void *plan = p;
-    p += sparse_plan_bytes(n);
+    const size_t plan_bytes = sparse_plan_bytes(n);
+    p += plan_bytes;
     L.trace_dev = scal + 1;
     L.status_dev = (int32_t *)(scal + 2 + B);
     L.wide_dev = (int32_t *)(scal + 3 + B);
@@ -271,9 +272,9 @@ static mpr_status start_build(Server &S, Ladder &L)
         int b = (B - 1) & 1;
         if (e == MPR_OK) e = copy_launch(A, ld, buf[b], ld, n, n, s);
         if (e == MPR_OK) e = normalise_launch(n, n, buf[b], ld, nullptr, nullptr, R[b], L.status_dev, nullptr, s);
-        if (e == MPR_OK && B >= 2) e = sparse_plan_launch(A, n, ld, plan, s);
+        if (e == MPR_OK && B >= 2) e = sparse_plan_launch(A, n, ld, plan, plan_bytes, L.status_dev, s);
         for (int k = 2; k <= B && e == MPR_OK; k++) {
-            e = sparse_step_launch(buf[b], ld, n, plan, buf[b ^ 1], ld, s);
+            e = sparse_step_launch(buf[b], ld, n, plan, plan_bytes, buf[b ^ 1], ld, s);
             if (e == MPR_OK)
                 e = normalise_launch(n, n, buf[b ^ 1], ld, R[b], nullptr, R[b ^ 1], L.status_dev, nullptr, s);
             b ^= 1;
@@ -282,10 +283,10 @@ static mpr_status start_build(Server &S, Ladder &L)
     // Baby steps: the canonical forms of (A^T)^j = (A^j)^T by the same chain
     // on A^T (plan built from the raw A^T before it is normalised in place).
     if (e == MPR_OK) e = transpose_launch(A, ld, L.Nb[1], ld, n, s);
-    if (e == MPR_OK && B >= 2) e = sparse_plan_launch(L.Nb[1], n, ld, plan, s);
+    if (e == MPR_OK && B >= 2) e = sparse_plan_launch(L.Nb[1], n, ld, plan, plan_bytes, L.status_dev, s);
     if (e == MPR_OK) e = normalise_launch(n, n, L.Nb[1], ld, nullptr, nullptr, L.Rb[1], L.status_dev, nullptr, s);
     for (int j = 2; j <= B && e == MPR_OK; j++) {
-        e = sparse_step_launch(L.Nb[j - 1], ld, n, plan, L.Nb[j], ld, s);
+        e = sparse_step_launch(L.Nb[j - 1], ld, n, plan, plan_bytes, L.Nb[j], ld, s);
         if (e == MPR_OK)
             e = normalise_launch(n, n, L.Nb[j], ld, L.Rb[j - 1], nullptr, L.Rb[j], L.status_dev, nullptr, s);
     }

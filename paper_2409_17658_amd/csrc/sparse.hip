@@ -100,11 +100,18 @@ __global__ __launch_bounds__(1024) void sp_order_kernel(const int64_t *counts, i
 
 // Ordered compaction of block J: idx[off[J] + t] = t-th row of L_J and
 // Bp[(off[J] + t) * SBN + c] = A[l][j0 + c]; padding rows are row 0 / infinite.
+// A plan whose rows (off[nblk]) exceed the capacity `cap` of its workspace
+// is not written: *st = MPR_ENOMEM, and the step kernel then does nothing.
 __global__ __launch_bounds__(256) void sp_fill_kernel(const u16 *A, int64_t lda, int64_t n, const int64_t *off,
-                                                      int32_t *idx, u16 *Bp, int vec)
+                                                      int64_t nblk, int64_t cap, int32_t *idx, u16 *Bp, int vec,
+                                                      int32_t *st)
 {
     __shared__ int wsum[4];
     __shared__ int64_t run;
+    if (off[nblk] > cap) {  // uniform over the grid
+        if (blockIdx.x == 0 && threadIdx.x == 0) set_status(st, MPR_ENOMEM);
+        return;
+    }
     const int64_t J = blockIdx.x, j0 = J * SBN;
     const int64_t base = off[J], end = off[J + 1];
     if (threadIdx.x == 0) run = 0;
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) v
                                                            const int32_t *__restrict__ order,
                                                            const int32_t *__restrict__ idx,
                                                            const u16 *__restrict__ Bp, u16 *__restrict__ C,
-                                                           int64_t ldc, int tiles_m, int nblk, int vec)
+                                                           int64_t ldc, int tiles_m, int nblk, int64_t cap, int vec)
 {
     __shared__ __attribute__((aligned(16))) u16 lds[SCfg::LDS_ELEMS];
     // Column blocks costliest first (order[]), all row tiles of one column
@@ -203,6 +210,18 @@ __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) v
     if (t >= tiles_m * nblk) return;
     const int tm = t % tiles_m, J = order[t / tiles_m];
     const int64_t m0 = (int64_t)tm * SCfg::BM, n0 = (int64_t)J * SBN;
+    if (off[nblk] > cap) {
+        // The plan did not fit its workspace (sp_fill_kernel reported it and
+        // wrote nothing): the output is all infinite, so no later pass reads
+        // stale values.
+        TileAcc<SCfg> none;
+#pragma unroll
+        for (int r = 0; r < SCfg::TM; r++)
+#pragma unroll
+            for (int q = 0; q < SCfg::NACC; q++) none.v[r][q] = (u16x2){0xFFFF, 0xFFFF};
+        tile_store<SCfg>(C, ldc, n, n, m0, n0, vec != 0, none);
+        return;
+    }
     const int64_t kbeg = off[J], K = off[J + 1] - kbeg;
     const gu16 *gN = glob(Np);
     const __attribute__((address_space(1))) int32_t *gi = glob(idx) + kbeg;
@@ -215,26 +234,54 @@ __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) v
 }
 
 // ------------------------------------------------------------ host side
+// Plan layout: counts[nblk + 1] | off[nblk + 1] | order[nblk] | idx[cap] |
+// Bp[cap * SBN], every piece 256-byte aligned; cap (rows) follows from the
+// bytes the caller gives the plan.  Its rows are sum_J |L_J| rounded up to
+// SBK per block, at most nblk * round_up(n, SBK) (the worst case, a dense
+// A); a transfer matrix needs a few per cent of that.
+static int64_t plan_fixed_bytes(int64_t nblk)
+{
+    return round_up((nblk + 1) * 8, 256) * 2 + round_up(nblk * 4, 256);
+}
+
+size_t sparse_plan_bytes_rows(int64_t n, int64_t rows)
+{
+    const int64_t nblk = (n + SBN - 1) / SBN;
+    return (size_t)(plan_fixed_bytes(nblk) + round_up(rows * 4, 256) + round_up(rows * SBN * 2, 256) + 256);
+}
+
 size_t sparse_plan_bytes(int64_t n)
 {
     const int64_t nblk = (n + SBN - 1) / SBN;
-    const int64_t rows = nblk * round_up(n, SBK);  // bound on sum of padded |L_J|
-    return (size_t)round_up((nblk + 1) * 8, 256) * 2 + (size_t)round_up(nblk * 4, 256) +
-           (size_t)round_up(rows * 4, 256) + (size_t)round_up(rows * SBN * 2, 256) + 256;
+    return sparse_plan_bytes_rows(n, nblk * round_up(n, SBK));
+}
+
+// Rows a plan workspace of `bytes` holds: the largest cap with
+// sparse_plan_bytes_rows(n, cap) <= bytes (so a workspace sized for `rows`
+// rows holds at least `rows`).  The first guess is at least that cap and
+// the roundings to 256 bytes take it at most a few rows past it.
+static int64_t plan_capacity(int64_t n, size_t bytes)
+{
+    const int64_t nblk = (n + SBN - 1) / SBN;
+    const int64_t avail = (int64_t)bytes - plan_fixed_bytes(nblk) - 256;
+    if (avail <= 0) return 0;
+    int64_t cap = avail / (4 + SBN * 2);
+    while (cap > 0 && sparse_plan_bytes_rows(n, cap) > bytes) cap--;
+    return cap;
 }
 
 struct SparsePlan {
-    int64_t nblk;
+    int64_t nblk, cap;
     int64_t *counts, *off;
     int32_t *order, *idx;
     u16 *Bp;
 };
 
-static SparsePlan carve_plan(void *ws, int64_t n)
+static SparsePlan carve_plan(void *ws, int64_t n, size_t bytes)
 {
     SparsePlan p;
     p.nblk = (n + SBN - 1) / SBN;
-    const int64_t rows = p.nblk * round_up(n, SBK);
+    p.cap = plan_capacity(n, bytes);
     char *c = (char *)ws;
     p.counts = (int64_t *)c;
     c += round_up((p.nblk + 1) * 8, 256);
@@ -243,28 +290,48 @@ static SparsePlan carve_plan(void *ws, int64_t n)
     p.order = (int32_t *)c;
     c += round_up(p.nblk * 4, 256);
     p.idx = (int32_t *)c;
-    c += round_up(rows * 4, 256);
+    c += round_up(p.cap * 4, 256);
     p.Bp = (u16 *)c;
     return p;
 }
 
-mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, hipStream_t s)
+// The counts and their prefix sums only (off[nblk] = the plan's rows).
+static void plan_count(const u16 *A, int64_t n, int64_t lda, const SparsePlan &p, hipStream_t s)
 {
-    SparsePlan p = carve_plan(ws, n);
     const int vec = aligned16(A) && lda % 8 == 0;
     hipLaunchKernelGGL(sp_count_kernel, dim3((unsigned)p.nblk), dim3(256), 0, s, A, lda, n, p.counts, vec);
     hipLaunchKernelGGL(sp_scan_kernel, dim3(1), dim3(1024), 0, s, (const int64_t *)p.counts, p.nblk, p.off);
+}
+
+mpr_status sparse_plan_rows(const u16 *A, int64_t n, int64_t lda, void *ws, hipStream_t s, int64_t *rows)
+{
+    SparsePlan p = carve_plan(ws, n, 0);
+    plan_count(A, n, lda, p, s);
+    if (check_launch() != MPR_OK) return MPR_EHIP;
+    if (hipMemcpyAsync(rows, p.off + p.nblk, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return MPR_EHIP;
+    return MPR_OK;
+}
+
+mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, size_t bytes, int32_t *st,
+                              hipStream_t s)
+{
+    SparsePlan p = carve_plan(ws, n, bytes);
+    const int vec = aligned16(A) && lda % 8 == 0;
+    plan_count(A, n, lda, p, s);
     hipLaunchKernelGGL(sp_order_kernel, dim3(1), dim3(1024), 0, s, (const int64_t *)p.counts, p.nblk, p.order);
     hipLaunchKernelGGL(sp_fill_kernel, dim3((unsigned)p.nblk), dim3(256), 0, s, A, lda, n, (const int64_t *)p.off,
-                       p.idx, p.Bp, vec);
+                       p.nblk, p.cap, p.idx, p.Bp, vec, st);
     return check_launch();
 }
 
 static std::atomic<int> g_sparse_arith{MPR_ARITH_U16};  // process-wide, set from any thread
 
-mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u16 *C, int64_t ldc, hipStream_t s)
+mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, size_t bytes, u16 *C, int64_t ldc,
+                              hipStream_t s)
 {
-    SparsePlan p = carve_plan(ws, n);
+    SparsePlan p = carve_plan(ws, n, bytes);
     const int64_t tiles_m = (n + SCfg::BM - 1) / SCfg::BM;
     const int64_t tiles = tiles_m * p.nblk;
     if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
@@ -272,7 +339,7 @@ mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, u
     auto kernel = g_sparse_arith == MPR_ARITH_F16 ? sp_step_kernel<true> : sp_step_kernel<false>;
     hipLaunchKernelGGL(kernel, dim3((unsigned)tiles), dim3(SCfg::NT), 0, s, Np, ldn, n, (const int64_t *)p.off,
                        (const int32_t *)p.order, (const int32_t *)p.idx, (const u16 *)p.Bp, C, ldc, (int)tiles_m,
-                       (int)p.nblk, vec);
+                       (int)p.nblk, p.cap, vec);
     return check_launch();
 }
 

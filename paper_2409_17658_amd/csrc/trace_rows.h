@@ -14,7 +14,7 @@ namespace mpr {
 
 constexpr uint32_t TR_NONE = 0xFFFFFFFFu;  // no finite term
 constexpr int TR_ROWS = 4;                 // rows per block of 256 threads: one per wave
-constexpr int TR_TRIP = 4;                 // 8-value chunks per lane in flight per trip
+constexpr int TR_TRIP = 8;                 // 16-byte chunks of each row per lane in flight per trip
 
 __device__ __forceinline__ uint32_t tr_term(uint32_t x, uint32_t y, uint32_t best)
 {
@@ -37,7 +37,9 @@ __device__ __forceinline__ uint32_t tr_min8(uint4 a, uint4 b, uint32_t best)
 // Wave-wide min over l < n of x[l] + y[l] for one row (TR_NONE when every
 // term has an infinite operand), returned to every lane.  `vec`: both rows
 // 16-byte aligned.  Lane t reads the chunks at 8t, 8t + 512, ...; each trip
-// issues TR_TRIP chunks of both rows before using any.
+// issues up to TR_TRIP chunks of both rows before using any (chunks past
+// the row's end are not loaded and count as infinite), so a row takes
+// ceil(chunks per lane / TR_TRIP) memory round trips, the last one included.
 __device__ __forceinline__ uint32_t tr_row_min(const u16 *x, const u16 *y, int64_t n, bool vec)
 {
     const int lane = (int)(threadIdx.x & 63);
@@ -46,18 +48,18 @@ __device__ __forceinline__ uint32_t tr_row_min(const u16 *x, const u16 *y, int64
     int64_t tail = 0;
     if (vec) {
         const int64_t n8 = n & ~(int64_t)7;
-        int64_t c = (int64_t)lane * 8;
-        for (; c + (TR_TRIP - 1) * 512 < n8; c += TR_TRIP * 512) {
+        const uint4 inf = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        for (int64_t c = (int64_t)lane * 8; c < n8; c += TR_TRIP * 512) {
             uint4 a[TR_TRIP], b[TR_TRIP];
 #pragma unroll
             for (int q = 0; q < TR_TRIP; q++) {
-                a[q] = gload16(gx + c + q * 512);
-                b[q] = gload16(gy + c + q * 512);
+                const bool in = c + q * 512 < n8;
+                a[q] = in ? gload16(gx + c + q * 512) : inf;
+                b[q] = in ? gload16(gy + c + q * 512) : inf;
             }
 #pragma unroll
             for (int q = 0; q < TR_TRIP; q++) best = tr_min8(a[q], b[q], best);
         }
-        for (; c < n8; c += 512) best = tr_min8(gload16(gx + c), gload16(gy + c), best);
         tail = n8;
     }
     for (int64_t c = tail + lane; c < n; c += 64) best = tr_term(gx[c], gy[c], best);
@@ -126,7 +128,8 @@ __device__ __forceinline__ u16x2 tr8_min16(uint4 a, uint4 b, u16x2 best)
 
 // Wave-wide min over l < n of x[l] + y[l] for one row of bytes (TR_NONE when
 // every term has an infinite operand), returned to every lane.  `vec`: both
-// rows 16-byte aligned.
+// rows 16-byte aligned.  Trips as in tr_row_min (a chunk past the row's end
+// reads as 0xFF bytes, infinite).
 __device__ __forceinline__ uint32_t tr8_row_min(const uint8_t *x, const uint8_t *y, int64_t n, bool vec)
 {
     const int lane = (int)(threadIdx.x & 63);
@@ -136,19 +139,18 @@ __device__ __forceinline__ uint32_t tr8_row_min(const uint8_t *x, const uint8_t 
     int64_t tail = 0;
     if (vec) {
         const int64_t n16 = n & ~(int64_t)15;
-        int64_t c = (int64_t)lane * 16;  // this lane's chunks: c, c + 1024, ...
-        for (; c + (TR_TRIP - 1) * 1024 < n16; c += TR_TRIP * 1024) {
+        const uint4 inf = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        for (int64_t c = (int64_t)lane * 16; c < n16; c += TR_TRIP * 1024) {  // chunks c, c + 1024, ...
             uint4 a[TR_TRIP], b[TR_TRIP];
 #pragma unroll
             for (int q = 0; q < TR_TRIP; q++) {
-                a[q] = gload16((const gu16 *)(gx + c + q * 1024));
-                b[q] = gload16((const gu16 *)(gy + c + q * 1024));
+                const bool in = c + q * 1024 < n16;
+                a[q] = in ? gload16((const gu16 *)(gx + c + q * 1024)) : inf;
+                b[q] = in ? gload16((const gu16 *)(gy + c + q * 1024)) : inf;
             }
 #pragma unroll
             for (int q = 0; q < TR_TRIP; q++) best = tr8_min16(a[q], b[q], best);
         }
-        for (; c < n16; c += 1024)
-            best = tr8_min16(gload16((const gu16 *)(gx + c)), gload16((const gu16 *)(gy + c)), best);
         tail = n16;
     }
     uint32_t m = best.x < best.y ? best.x : best.y;

@@ -135,3 +135,30 @@ def test_sparse_chain_u16_digests(mpr):
             assert digest(N, R) == g["digest_sha256"][str(k)], k
     finally:
         mpr.set_sparse_arith("u16")
+
+
+def test_sparse_plan_sized_for_the_matrix(mpr):
+    """The compressed-K plan sized for the transfer matrix (a few per cent
+    of the dense worst case) gives the same powers; a plan share too small
+    for it is reported on the device (MPR_ENOMEM, nothing computed), and
+    refused on the host when no status word could report it."""
+    import torch
+
+    g = load(7)
+    A = mpr.build_transfer(7)
+    n = A.shape[0]
+    exact = mpr.sparse_plan_bytes(A)
+    worst = mpr.power_workspace_size(n, 26, mpr.CHAIN_SPARSE) - mpr.power_workspace_size(n, 26, mpr.CHAIN)
+    assert exact * 4 < worst  # m = 7: 2.4 MB against 13.3 MB (m = 10: about 30x)
+    base = mpr.power_workspace_size(n, 26, mpr.CHAIN) + 256
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    N, R = mpr.minplus_power(A, 26, mpr.CHAIN_SPARSE, ws=mpr.workspace(base + exact), d_status=st, check=False)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and digest(N, R) == g["digest_sha256"]["26"]
+    small = mpr.workspace(base + exact - 4096)
+    mpr.minplus_power(A, 26, mpr.CHAIN_SPARSE, N, R, ws=small, d_status=st, check=False)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 2  # MPR_ENOMEM
+    with pytest.raises(mpr.MprError) as e:
+        mpr.minplus_power(A, 26, mpr.CHAIN_SPARSE, N, R, ws=small, check=False)
+    assert e.value.status == 1  # no status word: refused before any launch

@@ -224,9 +224,16 @@ def test_build_refused_without_free_memory_then_retried(serve):
 
     with serve.Server(baby=8, max_n=40, max_batch=8, slots=1, hbm_budget_bytes=8 << 30) as S:
         assert S.query(3, 10)["status"] == 0
-        free, _ = torch.cuda.mem_get_info()
-        hog = torch.empty(max(0, free - (64 << 20)), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        hog = []  # take the device's free memory down to at most 128 MiB
         try:
+            for _ in range(64):
+                free, _ = torch.cuda.mem_get_info()
+                if free <= (128 << 20):
+                    break
+                hog.append(torch.empty(min(free - (64 << 20), 32 << 30), dtype=torch.uint8, device="cuda"))
+            assert torch.cuda.mem_get_info()[0] <= (128 << 20)
             r1 = S.query(4, 20)
         finally:
             del hog
