@@ -198,6 +198,25 @@ mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t lda, int64_t 
                              int schedule, uint16_t *N_out, int64_t ldo, int64_t *R_out,
                              void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as mpr_minplus_power, with its workspace taken from a fixed
+ * device array of MPR_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends (its address on each device is
+ * recorded by mpr_init / the first call there).  The caller still passes A,
+ * N_out, R_out and d_status (same meaning, layout and errors as
+ * mpr_minplus_power).  Returns MPR_ENOMEM, before launching anything, when
+ * mpr_power_workspace_size(n, e, schedule) exceeds the array (for example
+ * n > 5792 for MPR_CHAIN); allocates nothing and calls no allocating
+ * routine.  The array keeps the last call's contents (nothing in it needs
+ * clearing: every call writes what it reads).  All calls on one GPU share
+ * the array, so calls that overlap on that GPU (other streams, other host
+ * threads) race and give unspecified results: serialise them. */
+#define MPR_NOALLOC_SCRATCH_BYTES (64u << 20)
+mpr_status mpr_minplus_power_noalloc(const uint16_t *A, int64_t n, int64_t lda, int64_t e, int schedule,
+                                     uint16_t *N_out, int64_t ldo, int64_t *R_out, int32_t *d_status,
+                                     mpr_stream stream);
+
 /* Bytes of the compressed-K plan of the n x n device matrix A (row stride
  * lda): for every block J of 64 columns, the rows of A with a finite entry
  * in J (rounded up to 32 per block) and their packed entries -- a few per

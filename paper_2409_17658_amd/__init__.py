@@ -90,6 +90,7 @@ _SIGS = {
                                    _P, _SZ, _P, _P]),
     "mpr_power_workspace_size": (_I, [_I64, _I64, _I, _P]),
     "mpr_minplus_power": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _SZ, _P, _P]),
+    "mpr_minplus_power_noalloc": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _P]),
     "mpr_sparse_plan_bytes": (_I, [_P, _I64, _I64, _P, _P]),
     "mpr_trace_min": (_I, [_P, _I64, _I64, _P, _P, _P]),
     "mpr_trace_of_product": (_I, [_P, _P, _P, _P, _I64, _I64, _P, _P]),
@@ -344,6 +345,18 @@ def minplus_power(A, e: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=N
                                 _ptr(ws), ws.numel(), _ptr(st), _stream(stream)), "mpr_minplus_power")
     if check and d_status is None:
         check_status(st)
+    return N_out, R_out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def minplus_power_noalloc(A, e: int, schedule: int, N_out, R_out, d_status=None, stream=None):
+    """mpr_minplus_power on the library's fixed device scratch (no workspace,
+    no allocation by the library); N_out / R_out are the caller's."""
+    n = A.shape[0]
+    _ok(lib().mpr_minplus_power_noalloc(_ptr(A), n, _ld(A), e, schedule, _ptr(N_out), _ld(N_out), _vptr(R_out, n),
+                                        _ptr(d_status), _stream(stream)), "mpr_minplus_power_noalloc")
     return N_out, R_out
 
 

@@ -26,13 +26,21 @@ mpr_status check_launch()
     return hipGetLastError() == hipSuccess ? MPR_OK : MPR_EHIP;
 }
 
+// Device memory of the allocation-free power entry point
+// (mpr_minplus_power_noalloc): a fixed array that every GPU the library runs
+// on holds from module load until the process ends.  Host code never uses
+// its name as an address; it uses the per-device address that init records.
+__device__ __align__(256) unsigned char scratch[MPR_NOALLOC_SCRATCH_BYTES];
+
 static std::mutex g_init_mu;
 static std::vector<int> g_cus;  // per device: CU count, 0 = not gfx950, -1 = unknown
+static std::vector<void *> g_scratch;   // per device: device address of `scratch`, nullptr if unknown
 
 static mpr_status init_device(int dev)
 {
     std::lock_guard<std::mutex> lk(g_init_mu);
     if ((int)g_cus.size() <= dev) g_cus.resize(dev + 1, -1);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
     if (g_cus[dev] > 0) return MPR_OK;
     if (g_cus[dev] == 0) return MPR_EUNSUPPORTED;
     hipDeviceProp_t prop;
@@ -41,8 +49,30 @@ static mpr_status init_device(int dev)
         g_cus[dev] = 0;
         return MPR_EUNSUPPORTED;
     }
+    // The scratch array's address on this device, taken with the device
+    // current (each GPU holds its own copy at its own address).
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return MPR_EHIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return MPR_EHIP;
+    void *p = nullptr;
+    const hipError_t se = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev && hipSetDevice(cur) != hipSuccess) return MPR_EHIP;
+    if (se != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the next launch check
+        p = nullptr;
+    }
+    g_scratch[dev] = p;
     g_cus[dev] = prop.multiProcessorCount;
     return MPR_OK;
+}
+
+// Address of the current device's scratch copy (nullptr when unavailable).
+static void *device_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    return dev < (int)g_scratch.size() ? g_scratch[dev] : nullptr;
 }
 
 mpr_status ensure_init()
@@ -408,6 +438,23 @@ extern "C" mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t ld
     if ((r = validate_launch(A, n, n, lda, d_status, s)) != MPR_OK) return r;
     if (schedule == MPR_SQUARE) return power_square(A, n, lda, e, N_out, ldo, R_out, w, d_status, s);
     return power_chain(A, n, lda, e, N_out, ldo, R_out, w, d_status, s, schedule == MPR_CHAIN_SPARSE);
+}
+
+extern "C" mpr_status mpr_minplus_power_noalloc(const uint16_t *A, int64_t n, int64_t lda, int64_t e, int schedule,
+                                                uint16_t *N_out, int64_t ldo, int64_t *R_out, int32_t *d_status,
+                                                mpr_stream stream)
+{
+    if (n < 0 || e < 1 || schedule < MPR_CHAIN || schedule > MPR_CHAIN_SPARSE) return MPR_EINVAL;
+    if (n && (!A || !N_out || !R_out)) return MPR_EINVAL;
+    if (!ld_ok(lda, n) || !ld_ok(ldo, n)) return MPR_EINVAL;
+    if (n == 0) return MPR_OK;
+    if (carve_power(nullptr, n, schedule).bytes > (size_t)MPR_NOALLOC_SCRATCH_BYTES) return MPR_ENOMEM;
+    mpr_status r = ensure_init();
+    if (r != MPR_OK) return r;
+    void *ws = device_scratch();
+    if (!ws) return MPR_EHIP;
+    return mpr_minplus_power(A, n, lda, e, schedule, N_out, ldo, R_out, ws, (size_t)MPR_NOALLOC_SCRATCH_BYTES,
+                             d_status, stream);
 }
 
 extern "C" mpr_status mpr_sparse_plan_bytes(const uint16_t *A, int64_t n, int64_t lda, size_t *bytes_host,
