@@ -85,6 +85,10 @@ def cpu_baseline_gemm(X, Y, target_s: float = 15.0):
                       (more, n, more, n, n, dt3)}
 
 
+def _dtype(arith: str) -> str:
+    return "uint16" if arith == "u16" else "f16"
+
+
 def _events(torch, k):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
 
@@ -151,7 +155,7 @@ def bench_gemm(args, mpr, torch):
     value = pairs / (ms_step * 1e-3) / 1e9
     achieved = pairs / (kern_avg * 1e-3) / 1e9
     peak = valu_peak_gpairs(cus, info["arith"])
-    dtype = "uint16" if info["arith"] == "u16" else "f16"
+    dtype = _dtype(info["arith"])
 
     def tile_name(i):
         return "%dx%d, %dx%d per lane, %d threads, %s arithmetic" % (i["bm"], i["bn"], i["tm"], i["tn"],
@@ -322,7 +326,7 @@ def bench_config2(args, mpr, torch):
     pairs = float(n) ** 3
     return {"metric": "min-plus GOPS, N=8192 single product and 64-power chain", "value": round(63 * pairs / t_chain / 1e9, 1),
             "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": mpr.gemm_config_info(mpr.gemm_pick_config(n, n, n))["arith"],
+            "dtype": _dtype(mpr.gemm_config_info(mpr.gemm_pick_config(n, n, n))["arith"]),
             "data": "synthetic (SplitMix64 seed 3; uniform [0,15], 30% infinity)",
             "config": {"workload": "A^64 by the chain, N=8192, normalised every step", "n": n, "e": e},
             "single_product_ms": round(t_single * 1e3, 3), "single_product_gpairs": round(pairs / t_single / 1e9, 1),
@@ -394,7 +398,7 @@ def bench_config3(args, mpr, torch):
         per_m[9] = bench_m9(mpr, torch)
     return {"metric": "Roman transfer powers to n=300 (m=6,7,8): chain GOPS", "value": round(tot / tt / 1e9, 1),
             "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": mpr.gemm_config_info(mpr.gemm_pick_config(7411, 7411, 7411))["arith"],
+            "dtype": _dtype(mpr.gemm_config_info(mpr.gemm_pick_config(7411, 7411, 7411))["arith"]),
             "data": "transfer matrices",
             "config": {"workload": "A(G)^300 by chain and by squaring, period search, gamma_R(3..300)"},
             "per_m": per_m}
@@ -460,7 +464,7 @@ def bench_m10(args, mpr, torch):
     gam = {k: int(tr[k]) for k in range(3, kmax + 1)}
     out = {"metric": "gamma_R(P_10 x C_n): seconds for the m=10 period search (A^1..A^kmax, N=64769)",
            "value": round(t, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False,
-           "dtype": "f16" if args.m10_sparse else mpr.gemm_config_info(mpr.gemm_pick_config(n, n, n))["arith"],
+           "dtype": "uint16" if mpr.get_arith() == "u16" else "f16",
            "data": "transfer matrix m=10",
            "dense_equivalent_gpairs": round((kmax - 1) * float(n) ** 3 / t / 1e9, 1),
            "config": {"workload": "A(G)^k, k <= %d, N=64769, ring of 8 powers" % kmax, "n": n,
@@ -566,7 +570,7 @@ def bench_config4(args, mpr, torch):
     binfo = mpr.batch_config_info(best)
     return {"metric": "batched min-plus power chains GOPS (256 chains, one launch in a HIP graph)",
             "value": round(pairs / t_batch / 1e9, 1), "unit": "G pairs/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": binfo["arith"], "data": "synthetic (batch_instances seed 4; entries U[0,31], 25% infinity)",
+            "dtype": _dtype(binfo["arith"]), "data": "synthetic (batch_instances seed 4; entries U[0,31], 25% infinity)",
             "config": {"workload": "256 chains, N log-uniform [256,4096], e uniform [8,128]",
                        "total_pairs": pairs, "batch_config": best, "panel_rows": binfo["panel_rows"],
                        "per_instance_tile_configs": sorted({mpr.gemm_pick_config(d["n"], d["n"], d["n"])
