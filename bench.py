@@ -180,6 +180,19 @@ def bench_gemm(args, mpr, torch):
                          if info["arith"] == "u16" else "2 v_pk_add_f16 + 1 v_pk_minimum3_f16: 4 pairs per 3")},
         "input_gen_s": round(gen_s, 1),
     }
+    if args.probe:
+        # the instruction mix's own rate on this device, and the clock it ran at
+        # (pairs per CU per clock = the issue rate the peak assumes: 64 for
+        # uint16, 85.33 for the f16 form; the probe's clock is its own, a
+        # pure-VALU load runs a little below the product's)
+        probe = {}
+        for a in ("u16", "f16"):
+            rate, ghz = mpr.valu_probe(a, args.probe_iters)
+            nominal = valu_peak_gpairs(cus, a)
+            probe[a] = {"gpairs": round(rate / 1e9, 1), "frac_of_nominal_peak": round(rate / 1e9 / nominal, 4),
+                        "clock_ghz": round(ghz, 3), "pairs_per_cu_clock": round(rate / (cus * ghz * 1e9), 2),
+                        "nominal_pairs_per_cu_clock": round(nominal / (cus * PEAK_CLOCK_GHZ), 2)}
+        out["valu_probe"] = probe
     if args.f16_form and info["arith"] == "u16":
         out["f16_form"] = bench_f16_form(args, mpr, torch, timed_steps, tile_name, cus, pairs, n, L, sptr)
     if not args.skip_cpu_baseline:
@@ -483,6 +496,66 @@ def bench_m10(args, mpr, torch):
         out["remark13_ok"] = all(ext(k) == 2 * (m + 1) * k // 5 for k in range(5, 2001, 5))
         out["theorem11_ok"] = all(ext(k) >= -(-2 * (m + 1) * k // 5) for k in range(10, 2001))
     gd = os.path.join(ROOT, "tests", "golden", "rowdp_m10.json")
+    if os.path.exists(gd):
+        with open(gd) as f:
+            rd = {int(k): v for k, v in json.load(f)["gamma"].items()}
+        out["rowdp_golden_ok"] = all(gam[k] == v for k, v in rd.items() if k in gam)
+    return out
+
+
+# ---------------------------------------------------------------- m = 11
+def bench_m11(args, mpr, torch):
+    """gamma_R(P_11 x C_n) for every n: the m = 11 transfer matrix (191476
+    states, 73.3 GB per power) on one MI355X.  Three powers fit beside each
+    other, not a ring longer than the period, so the search keeps two
+    powers in its ring and A's own buffer (free once the compressed-K plan
+    replaces A) for the power at which a class repeat shows; the relation
+    is confirmed exactly one period later.  Checks: Remark 13 (2(m+1)n/5 for
+    5 | n), Theorem 11 (ceil(2(m+1)n/5) <= gamma for n >= 10) and the
+    oracle's row DP for small n (stored golden)."""
+    m, kmax = 11, args.m11_kmax
+    A = mpr.build_transfer(m)
+    n = A.shape[0]
+    torch.cuda.synchronize()
+    print("m11: transfer matrix built, %d states" % n, file=sys.stderr, flush=True)
+    plan_b = mpr.sparse_plan_bytes(A)
+    flags = mpr.PERIOD_SPARSE | mpr.PERIOD_EXTEND | mpr.PERIOD_REUSE_A
+    ws_b = mpr.period_workspace_size(n, 2, mpr.PERIOD_REUSE_A) + plan_b
+    ws = mpr.workspace(ws_b)
+    t_last = [time.perf_counter()]
+
+    def progress(k, trace):  # one line per power (each takes seconds)
+        now = time.perf_counter()
+        print("m11: power %d trace %d (%.1f s)" % (k, trace, now - t_last[0]), file=sys.stderr, flush=True)
+        t_last[0] = now
+
+    mpr.set_period_progress(progress)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu, lam, c, tr = mpr.find_period(A, kmax, traces=True, ws=ws, sparse=True, extend=True, reuse_a=True)
+        t = time.perf_counter() - t0
+    finally:
+        mpr.set_period_progress(None)
+    del A
+    computed = (mu + lam) if mu is not None else kmax
+    gam = {k: int(tr[k]) for k in range(3, kmax + 1)}
+    out = {"metric": "gamma_R(P_11 x C_n): seconds for the m=11 period search (N=191476)",
+           "value": round(t, 2), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "uint16" if mpr.get_arith() == "u16" else "f16", "data": "transfer matrix m=11",
+           "config": {"workload": "A(G)^k, N=191476, two ring powers + A's buffer, compressed-K steps", "n": n,
+                      "flags": "sparse, extend, reuse_a"},
+           "period": [mu, lam, c], "powers_computed": computed, "gamma": gam,
+           "workspace_gb": round(ws_b / 1e9, 2), "matrix_gb": round(n * mpr.round_up(n) * 2 / 1e9, 2),
+           "plan_gb": round(plan_b / 1e9, 3)}
+    if mu is not None:
+        numer = mpr.period_formula(mu, lam, c, tr[: mu + lam])
+        out["formula"] = {"valid_from": mu, "gamma(n)": "(%d n + numer[n mod %d]) / %d" % (c, lam, lam),
+                          "numer": numer.tolist()}
+        ext = lambda k: mpr.gamma_from_period(mu, lam, c, tr, k)
+        out["remark13_ok"] = all(ext(k) == 2 * (m + 1) * k // 5 for k in range(5, 2001, 5))
+        out["theorem11_ok"] = all(ext(k) >= -(-2 * (m + 1) * k // 5) for k in range(10, 2001))
+    gd = os.path.join(ROOT, "tests", "golden", "rowdp_m11.json")
     if os.path.exists(gd):
         with open(gd) as f:
             rd = {int(k): v for k, v in json.load(f)["gamma"].items()}
@@ -954,13 +1027,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--cfg", type=int, default=-1, help="tile configuration (-1: tile table)")
-    ap.add_argument("--workload", default="gemm", choices=["gemm", "config2", "config3", "config4", "serve", "m10"])
+    ap.add_argument("--workload", default="gemm",
+                    choices=["gemm", "config2", "config3", "config4", "serve", "m10", "m11"])
+    ap.add_argument("--m11-kmax", type=int, default=45)
     ap.add_argument("--m10-kmax", type=int, default=35)
     ap.add_argument("--with-m9", type=int, default=1, help="config3: also the m = 9 run")
     ap.add_argument("--m10-sparse", type=int, default=1)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--f16-form", type=int, default=1, help="also time the step in the f16 form (labelled)")
     ap.add_argument("--slow-reps", type=int, default=3)
+    ap.add_argument("--probe", type=int, default=1, help="measure the VALU rate of both instruction mixes")
+    ap.add_argument("--probe-iters", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson query stream in the default run (0: none)")
@@ -1018,6 +1095,8 @@ def main():
         out = bench_config4(args, mpr, torch)
     elif args.workload == "m10":
         out = bench_m10(args, mpr, torch)
+    elif args.workload == "m11":
+        out = bench_m11(args, mpr, torch)
     else:
         out = {"metric": "gamma_R query serving, Poisson 200 req/s, m in 3..9, n in 3..1000",
                "unit": "ms", "n_gpus": 1, "higher_is_better": False}

@@ -66,6 +66,9 @@ typedef enum {
 #define MPR_PERIOD_SPARSE 1 /* mpr_find_period_ex flag: compressed-K chain steps */
 #define MPR_PERIOD_EXTEND 2 /* mpr_find_period_ex flag: stop at the confirmed
                                period and extend the traces by it */
+#define MPR_PERIOD_REUSE_A 4 /* mpr_find_period_ex flag: A's buffer may be
+                                overwritten to hold a power (needs
+                                MPR_PERIOD_SPARSE) */
 
 /* Arithmetic of a product configuration.  MPR_ARITH_U16: packed uint16
  * saturating add and min.  MPR_ARITH_F16: the operands' f16 images (a
@@ -288,6 +291,12 @@ mpr_status mpr_find_period(const uint16_t *A, int64_t n, int64_t lda, int64_t km
                            int64_t *mu_host, int64_t *lam_host, int64_t *c_host,
                            int64_t *traces_host, void *ws, size_t ws_bytes, mpr_stream stream);
 
+/* Installs a process-wide observer of the period search: fn(k, trace, user)
+ * is called on the searching thread after every power A^k it computes
+ * (trace = its trace, MPR_ROW_NONE if none), e.g. to report progress of a
+ * search that runs for minutes.  fn = NULL removes it. */
+mpr_status mpr_set_period_progress(void (*fn)(int64_t k, int64_t trace, void *user), void *user);
+
 /* Proposition 8 and the finite-difference solution that follows it: with
  * A^(mu+lam) = c (x) A^mu, gamma(n + lam) = gamma(n) + c for n >= mu, so
  *   gamma(n) = traces[mu + (n - mu) mod lam] + c * floor((n - mu) / lam)
@@ -314,7 +323,16 @@ mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t 
  * lambda, as Algorithm 2 does) instead of computing every power to kmax,
  * and fills traces_host[k] for mu + lambda < k <= kmax from the relation
  * A^(k) = c (x) A^(k - lambda), k - lambda >= mu (Lemma 2):
- * trace(k) = trace(k - lambda) + c, exact (MPR_ROW_NONE stays). */
+ * trace(k) = trace(k - lambda) + c, exact (MPR_ROW_NONE stays).
+ * MPR_PERIOD_REUSE_A (with MPR_PERIOD_SPARSE; lda must be round_up(n, 8))
+ * is for matrices too large for a ring longer than the period: once the
+ * compressed-K plan has replaced A, A's buffer (whose contents are then
+ * lost) keeps the power at which a class repeat the ring can no longer
+ * confirm was seen, and the repeat is confirmed exactly one period later.
+ * *mu_host is then that power's index, the smallest power at which the
+ * relation A^(mu+lam) = c (x) A^mu has been checked exactly (at most lam
+ * above the least pre-period, which the class hashes place lam below it);
+ * lam and c are the least period and its exact offset. */
 mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host);
 mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int flags,
                               int64_t *mu_host, int64_t *lam_host, int64_t *c_host, int64_t *traces_host,
@@ -485,6 +503,19 @@ mpr_status mpr_server_destroy(void *server);
 /* ------------------------------------------------------------------ */
 /* Tile configurations and the autotuner's table.                      */
 /* ------------------------------------------------------------------ */
+
+/* Measures the issue rate of a product's instruction mix on the current
+ * device (MPR_ARITH_U16: v_pk_add_u16 clamp + v_pk_min_u16; MPR_ARITH_F16:
+ * 2 v_pk_add_f16 + 1 v_pk_minimum3_f16): a register-only kernel with 8
+ * waves per SIMD on every CU, each lane running independent accumulator
+ * chains `iters` times (1 <= iters <= 2^24).  *pairs_per_s_host receives the
+ * (add, min) pairs per second by HIP events; *clock_ghz_host the shader
+ * clock during the run, from the cycle counter and the constant-rate wall
+ * clock of one wave.  Confirms the VALU peak the kernels are priced
+ * against.  Synchronous; allocates (and frees) 256 bytes of device memory,
+ * so not for a hot path. */
+mpr_status mpr_valu_probe(int arith, int iters, double *pairs_per_s_host, double *clock_ghz_host,
+                          mpr_stream stream);
 
 /* Number of compiled (min,+) tile configurations. */
 int mpr_gemm_config_count(void);

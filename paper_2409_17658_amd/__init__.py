@@ -32,6 +32,7 @@ SQUARE = 1
 CHAIN_SPARSE = 2
 PERIOD_SPARSE = 1
 PERIOD_EXTEND = 2
+PERIOD_REUSE_A = 4
 ARITH_U16 = 0
 ARITH_F16 = 1
 
@@ -100,6 +101,7 @@ _SIGS = {
     "mpr_period_workspace_size_ex": (_I, [_I64, _I64, _I, _P]),
     "mpr_find_period_ex": (_I, [_P, _I64, _I64, _I64, _I, _P, _P, _P, _P, _P, _SZ, _P]),
     "mpr_gamma_from_period": (_I, [_I64, _I64, _I64, _P, _I64, _I64, _P]),
+    "mpr_set_period_progress": (_I, [_P, _P]),
     "mpr_period_formula": (_I, [_I64, _I64, _I64, _P, _I64, _P]),
     "mpr_batch_workspace_size": (_I, [_P, _I, _P]),
     "mpr_batch_plan": (_I, [_P, _I, _P, _SZ, _P]),
@@ -130,6 +132,7 @@ _SIGS = {
     "mpr_set_tile_table": (_I, [_P, _P, _I]),
     "mpr_gemm_pick_config": (_I, [_I64, _I64, _I64]),
     "mpr_autotune_gemm": (_I, [_I64, _I, _P, _P, _P]),
+    "mpr_valu_probe": (_I, [_I, _I, _P, _P, _P]),
 }
 
 
@@ -404,17 +407,18 @@ def period_workspace_size(n: int, slots: int, flags: int = 0) -> int:
 
 
 def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None, sparse: bool = False,
-                extend: bool = False):
+                extend: bool = False, reuse_a: bool = False):
     """(mu, lam, c, traces) with traces[k] = trace of A^k for k = 1..kmax
     (None when traces=False); mu is None when no period is confirmed.
     sparse=True runs the chain steps over the compressed rows of A;
     extend=True stops at the confirming power and fills the later traces
-    from the period (exact)."""
+    from the period (exact); reuse_a=True (with sparse) lets the search
+    overwrite A to confirm a period longer than the ring one period late."""
     n = A.shape[0]
-    flags = (PERIOD_SPARSE if sparse else 0) | (PERIOD_EXTEND if extend else 0)
+    flags = (PERIOD_SPARSE if sparse else 0) | (PERIOD_EXTEND if extend else 0) | (PERIOD_REUSE_A if reuse_a else 0)
     if ws is None:  # with sparse=True the plan is sized for this A
-        ws = workspace(period_workspace_size(n, slots, 0) + (sparse_plan_bytes(A, stream) if sparse else 0),
-                       A.device)
+        ws = workspace(period_workspace_size(n, slots, flags & PERIOD_REUSE_A) +
+                       (sparse_plan_bytes(A, stream) if sparse else 0), A.device)
     mu, lam, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     tr = np.zeros(kmax + 1, dtype=np.int64) if traces else None
     st = lib().mpr_find_period_ex(_ptr(A), n, _ld(A), kmax, flags, ctypes.byref(mu), ctypes.byref(lam),
@@ -424,6 +428,22 @@ def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, str
         return None, None, None, tr
     _ok(st, "mpr_find_period")
     return mu.value, lam.value, c.value, tr
+
+
+_PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p)
+_progress_keep = None
+
+
+def set_period_progress(fn=None):
+    """fn(k, trace) after every power of a period search (None: off)."""
+    global _progress_keep
+    if fn is None:
+        _ok(lib().mpr_set_period_progress(None, None), "mpr_set_period_progress")
+        _progress_keep = None
+        return
+    cb = _PROGRESS_FN(lambda k, t, _u: fn(int(k), int(t)))
+    _ok(lib().mpr_set_period_progress(ctypes.cast(cb, ctypes.c_void_p), None), "mpr_set_period_progress")
+    _progress_keep = cb  # the C side keeps the pointer: keep the callback alive
 
 
 def gamma_from_period(mu: int, lam: int, c: int, traces, n: int) -> int:
@@ -613,3 +633,12 @@ def autotune_gemm(n: int, reps: int = 3, stream=None):
     best = ctypes.c_int()
     _ok(lib().mpr_autotune_gemm(n, reps, ms, ctypes.byref(best), _stream(stream)), "mpr_autotune_gemm")
     return best.value, list(ms)
+
+
+def valu_probe(arith: str = "u16", iters: int = 20000, stream=None):
+    """(pairs per second, shader clock in GHz) of the instruction mix of
+    arithmetic form `arith`, measured on the device."""
+    r, c = ctypes.c_double(), ctypes.c_double()
+    _ok(lib().mpr_valu_probe(_arith_code(arith), iters, ctypes.byref(r), ctypes.byref(c), _stream(stream)),
+        "mpr_valu_probe")
+    return r.value, c.value

@@ -16,8 +16,8 @@ mpr_set_batch_weights as the weights of the library's schedule model.
 
 init() calls both loaders.
 
-    python -m paper_2409_17658_amd.autotune [N ...]      # product tables
-    python -m paper_2409_17658_amd.autotune batch [PATH]  # batch weights
+    python -m paper_2409_17658_amd.autotune [--out PATH] [N ...]   # product tables
+    python -m paper_2409_17658_amd.autotune [--out PATH] batch     # batch weights
 """
 from __future__ import annotations
 
@@ -162,8 +162,14 @@ def load_batch_table(path: str = BATCH_TABLE) -> bool:
 
 
 if __name__ == "__main__":
-    if sys.argv[1:2] == ["batch"]:
-        print(json.dumps(tune_batch(path=sys.argv[2] if len(sys.argv) > 2 else BATCH_TABLE)["weights"]))
+    args = sys.argv[1:]
+    out = None
+    if "--out" in args:  # where to write the table (default: next to the library)
+        k = args.index("--out")
+        out = args[k + 1]
+        del args[k:k + 2]
+    if args[:1] == ["batch"]:
+        print(json.dumps(tune_batch(path=out or BATCH_TABLE)["weights"]))
     else:
-        sizes = [int(a) for a in sys.argv[1:]] or DEFAULT_SIZES
-        print(json.dumps(tune(sizes)["tables"]))
+        sizes = [int(a) for a in args] or DEFAULT_SIZES
+        print(json.dumps(tune(sizes, path=out or TABLE)["tables"]))

@@ -228,8 +228,27 @@ static mpr_status power_square(const u16 *A, int64_t n, int64_t lda, int64_t e, 
 }
 
 // ------------------------------------------------------------ period search
+// Process-wide observer of long period searches: called on the calling
+// thread after every power (its index and trace).
+static std::mutex g_progress_mu;
+static void (*g_progress_fn)(int64_t, int64_t, void *) = nullptr;
+static void *g_progress_user = nullptr;
+
+static void report_progress(int64_t k, int64_t trace)
+{
+    void (*fn)(int64_t, int64_t, void *);
+    void *user;
+    {
+        std::lock_guard<std::mutex> lk(g_progress_mu);
+        fn = g_progress_fn;
+        user = g_progress_user;
+    }
+    if (fn) fn(k, trace, user);
+}
+
 struct PeriodWs {
     uint64_t *row_hash;
+    int64_t *hold_R;  // offsets of the power kept in A's buffer (MPR_PERIOD_REUSE_A)
     void *plan;
     size_t plan_bytes;
     int64_t *scal;  // [0] hash, [1] trace, [2] status (int32 in low half), [3..5] compare
@@ -252,6 +271,7 @@ static PeriodWs carve_period(void *ws, int64_t n, size_t ws_bytes, int64_t slots
     Carver c(ws);
     w.row_hash = c.take<uint64_t>((size_t)n);
     w.scal = c.take<int64_t>(8);
+    w.hold_R = (flags & MPR_PERIOD_REUSE_A) ? c.take<int64_t>((size_t)n) : nullptr;
     if (flags & MPR_PERIOD_SPARSE) {
         w.plan_bytes = plan_bytes ? plan_bytes : sparse_plan_bytes(n);
         w.plan = (void *)c.take<char>(w.plan_bytes);
@@ -505,7 +525,8 @@ extern "C" mpr_status mpr_trace_of_product_t(const uint16_t *X, const int64_t *R
 
 extern "C" mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host)
 {
-    if (n < 0 || slots < 2 || !bytes_host || (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND))) return MPR_EINVAL;
+    if (n < 0 || slots < 2 || !bytes_host || (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND | MPR_PERIOD_REUSE_A)))
+        return MPR_EINVAL;
     PeriodWs w = carve_period(nullptr, n, 0, slots, flags);
     *bytes_host = w.fixed + (size_t)slots * w.slot_bytes;
     return MPR_OK;
@@ -521,8 +542,13 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
                                          void *ws, size_t ws_bytes, mpr_stream stream)
 {
     if (n < 1 || kmax < 1 || !A || !mu_host || !lam_host || !c_host || !ld_ok(lda, n)) return MPR_EINVAL;
-    if (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND)) return MPR_EINVAL;
+    if (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND | MPR_PERIOD_REUSE_A)) return MPR_EINVAL;
     const bool sparse = (flags & MPR_PERIOD_SPARSE) != 0;
+    const bool reuse_a = (flags & MPR_PERIOD_REUSE_A) != 0;
+    // A's buffer can hold a power only once nothing reads A any more (the
+    // compressed-K plan replaces it after the first power) and only in the
+    // ring's layout (the compare reads both powers with one row stride).
+    if (reuse_a && (!sparse || lda != round_up(n, 8))) return MPR_EINVAL;
     if (!ws) return MPR_ENOMEM;
     mpr_status r = ensure_init();
     if (r != MPR_OK) return r;
@@ -531,7 +557,7 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
     // one host round trip), so the ring gets every byte the plan does not use.
     size_t plan_bytes = 0;
     if (sparse) {
-        PeriodWs probe = carve_period(ws, n, ws_bytes, 0, 0);
+        PeriodWs probe = carve_period(ws, n, ws_bytes, 0, flags & ~MPR_PERIOD_SPARSE);  // the part before the plan
         if (ws_bytes < probe.fixed + sparse_plan_bytes_rows(n, 0)) return MPR_ENOMEM;
         int64_t rows = 0;
         if ((r = sparse_plan_rows(A, n, lda, (char *)ws + probe.fixed, s, &rows)) != MPR_OK) return r;
@@ -546,11 +572,34 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
     if (traces_host) traces_host[0] = MPR_ROW_NONE;
 
     // Power k lives in slot (k - 1) % slots (a ring), so a repeat of the class
-    // of power j can be confirmed exactly while k - j < slots.
+    // of power j can be confirmed exactly while k - j < slots.  With
+    // MPR_PERIOD_REUSE_A a repeat the ring can no longer confirm (power j
+    // gone) is confirmed one period later instead: power k is kept in A's
+    // buffer and compared with power k + (k - j) when the chain gets there.
     std::unordered_multimap<uint64_t, int64_t> seen;  // class hash -> k
     bool found = false;
     int64_t mu = 0, lam = 0, cval = 0;
     int64_t prev_slot = -1;
+    bool held = false;           // a power waits in A's buffer
+    int64_t held_k = 0, held_lam = 0;
+    u16 *hold_N = reuse_a ? const_cast<u16 *>(A) : nullptr;
+
+    // Exact comparison of (X, RX) with (Y, RY) (same N and emptiness, one
+    // offset shift c over the non-empty rows; c = 0 when no row has one).
+    auto same_class = [&](const u16 *X, const int64_t *RX, const u16 *Y, const int64_t *RY, bool &eq,
+                          int64_t &c) -> mpr_status {
+        int64_t *out3 = &w.scal[3];
+        mpr_status e = compare_launch(X, RX, Y, RY, n, w.ld, out3, s);
+        if (e != MPR_OK) return e;
+        int64_t cmp[3];
+        if (hipMemcpyAsync(cmp, out3, sizeof(cmp), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MPR_EHIP;
+        const bool no_rows = cmp[1] == MPR_ROW_NONE && cmp[2] == -MPR_ROW_NONE;
+        eq = cmp[0] == 0 && (cmp[1] == cmp[2] || no_rows);
+        c = no_rows ? 0 : cmp[1];
+        return MPR_OK;
+    };
     for (int64_t k = 1; k <= kmax; k++) {
         const int64_t slot = (k - 1) % w.slots;
         u16 *Nk = slot_N(w, slot);
@@ -573,29 +622,47 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
             return MPR_EHIP;
         if ((int32_t)(host[2] & 0xFFFFFFFF) != 0) return (mpr_status)(int32_t)(host[2] & 0xFFFFFFFF);
         if (traces_host) traces_host[k] = host[1];
+        report_progress(k, host[1]);
         prev_slot = slot;
+        if (!found && held && k == held_k + held_lam) {
+            // the power kept one period ago: the relation A^(k) = c (x)
+            // A^(k - lam) confirmed exactly at n0 = k - lam
+            bool eq = false;
+            int64_t c = 0;
+            if ((r = same_class(hold_N, w.hold_R, Nk, Rk, eq, c)) != MPR_OK) return r;
+            held = false;
+            if (eq) {
+                found = true;
+                mu = held_k;
+                lam = held_lam;
+                cval = c;
+            }
+        }
         if (!found) {
             const uint64_t h = (uint64_t)host[0];
             auto range = seen.equal_range(h);
             for (auto it = range.first; it != range.second && !found; ++it) {
                 const int64_t j = it->second;
-                if (k - j >= w.slots) continue;  // power j is no longer resident
-                int64_t *out3 = &w.scal[3];
+                if (k - j >= w.slots) {  // power j is no longer resident
+                    if (reuse_a && !held) {
+                        if ((r = copy_launch(Nk, w.ld, hold_N, lda, n, n, s)) != MPR_OK) return r;
+                        if (hipMemcpyAsync(w.hold_R, Rk, (size_t)n * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                            return MPR_EHIP;
+                        held = true;
+                        held_k = k;
+                        held_lam = k - j;
+                    }
+                    continue;
+                }
                 const int64_t sj = (j - 1) % w.slots;
-                if ((r = compare_launch(slot_N(w, sj), slot_R(w, sj), Nk, Rk, n, w.ld, out3, s)) != MPR_OK) return r;
-                int64_t cmp[3];
-                if (hipMemcpyAsync(cmp, out3, sizeof(cmp), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess)
-                    return MPR_EHIP;
-                // same N and emptiness (cmp[0] == 0) and one offset shift over
-                // the non-empty rows; with no non-empty row at all every shift
-                // fits and c = 0 is reported
-                const bool no_rows = cmp[1] == MPR_ROW_NONE && cmp[2] == -MPR_ROW_NONE;
-                if (cmp[0] == 0 && (cmp[1] == cmp[2] || no_rows)) {
+                bool eq = false;
+                int64_t c = 0;
+                if ((r = same_class(slot_N(w, sj), slot_R(w, sj), Nk, Rk, eq, c)) != MPR_OK) return r;
+                if (eq) {
                     found = true;
                     mu = j;
                     lam = k - j;
-                    cval = no_rows ? 0 : cmp[1];
+                    cval = c;
                 }
             }
             if (!found) seen.emplace(h, k);
@@ -611,6 +678,14 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
     *mu_host = mu;
     *lam_host = lam;
     *c_host = cval;
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_set_period_progress(void (*fn)(int64_t k, int64_t trace, void *user), void *user)
+{
+    std::lock_guard<std::mutex> lk(g_progress_mu);
+    g_progress_fn = fn;
+    g_progress_user = user;
     return MPR_OK;
 }
 

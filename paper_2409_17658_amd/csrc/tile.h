@@ -194,7 +194,10 @@ __device__ __forceinline__ void tile_kloop(int64_t nk, AOp &aop, BOp &bop, u16 *
             };
             if constexpr (!H) {
                 // B fragments of row kk + kq; the next row's are read while
-                // this one is consumed.
+                // this one is consumed.  The four sums of a column group are
+                // formed before its minima: a v_pk_min_u16 that reads the
+                // high-half-broadcast add issued just before it costs a wait
+                // state on gfx950.
                 uint4 bf[T::TN / 8], bn[T::TN / 8];
 #pragma unroll
                 for (int c8 = 0; c8 < T::TN / 8; c8++) bf[c8] = brow(kk, c8);
@@ -209,12 +212,16 @@ __device__ __forceinline__ void tile_kloop(int64_t nk, AOp &aop, BOp &bop, u16 *
                         const u16x2 ap = as_u16x2(comp(af[r], kq >> 1));
                         const u16x2 a2 = (kq & 1) ? ap.yy : ap.xx;
 #pragma unroll
-                        for (int c8 = 0; c8 < T::TN / 8; c8++)
+                        for (int c8 = 0; c8 < T::TN / 8; c8++) {
+                            u16x2 sum[4];
+#pragma unroll
+                            for (int q = 0; q < 4; q++) sum[q] = add_sat(a2, as_u16x2(comp(bf[c8], q)));
 #pragma unroll
                             for (int q = 0; q < 4; q++) {
                                 u16x2 &d = acc.v[r][c8 * 4 + q];
-                                d = min2(d, add_sat(a2, as_u16x2(comp(bf[c8], q))));
+                                d = min2(d, sum[q]);
                             }
+                        }
                     }
 #pragma unroll
                     for (int c8 = 0; c8 < T::TN / 8; c8++) bf[c8] = bn[c8];

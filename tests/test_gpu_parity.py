@@ -537,3 +537,19 @@ def test_find_period_not_found(mpr):
     mu, lam, c, tr = mpr.find_period(A, 10, traces=True)
     assert mu is None
     assert tr[10] == O.gamma(6, 10)
+
+
+def test_valu_probe_confirms_the_peak(mpr):
+    """The register-only probe of each form's instruction mix runs at or
+    below the nominal VALU peak the kernels are priced against (CUs x 64
+    lanes x 2.4 GHz x pairs per lane-instruction) and near it; the clock it
+    reports is a plausible shader clock."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for arith, per_lane_clk in (("u16", 1.0), ("f16", 4.0 / 3.0)):
+        rate, ghz = mpr.valu_probe(arith, 20000)
+        nominal = cus * 64 * per_lane_clk * 2.4e9
+        print("probe", arith, rate / 1e9, ghz, flush=True)
+        assert 0.7 * nominal < rate < 1.02 * nominal, (arith, rate, nominal)
+        assert 1.0 < ghz < 2.6
+    with pytest.raises(mpr.MprError):
+        mpr.valu_probe("u16", 0)

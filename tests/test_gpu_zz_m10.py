@@ -64,3 +64,35 @@ def test_m10_power_rows_match_oracle():
         print("m10 power", k, flush=True)
         assert np.array_equal(Nv[idx].cpu().numpy().view(np.uint16), want[k][0]), k
         assert np.array_equal(R[idx].cpu().numpy(), want[k][1]), k
+
+
+def test_m11_power_rows_match_oracle():
+    """m = 11 (191476 states, 73.3 GB per power): rows of A^2 and A^4 by the
+    compressed-K chain equal the oracle's row chain over the arcs of A."""
+    import oracle as O
+    import paper_2409_17658_amd as mpr
+
+    mpr.init(0)
+    torch.cuda.empty_cache()
+    m, ks = 11, (2, 4)
+    n = mpr.transfer_size(m)
+    rows = [0, 1, 17, 99999, 123456, n - 2, n - 1]
+    want = {}
+    O.chain_rows_sparse(O.transfer_rows(m, rows), O.transfer_arcs(m), max(ks),
+                        on_step=lambda k, N, R: want.__setitem__(k, (O.to_u16(N), R.copy())) if k in ks else None)
+    print("m11 oracle rows done", flush=True)
+    A = mpr.build_transfer(m)
+    ws = mpr.workspace(mpr.power_workspace_size(n, max(ks), mpr.CHAIN) + 256 + mpr.sparse_plan_bytes(A))
+    N = mpr.alloc_matrix(n, n)
+    R = torch.empty(n, dtype=torch.int64, device="cuda")
+    idx = torch.as_tensor(rows, device="cuda")
+    Nv = N.view(torch.int16)
+    try:
+        for k in ks:
+            mpr.minplus_power(A, k, mpr.CHAIN_SPARSE, N, R, ws, check=True)
+            print("m11 power", k, flush=True)
+            assert np.array_equal(Nv[idx].cpu().numpy().view(np.uint16), want[k][0]), k
+            assert np.array_equal(R[idx].cpu().numpy(), want[k][1]), k
+    finally:
+        del A, ws, N, R, Nv
+        torch.cuda.empty_cache()
