@@ -999,10 +999,12 @@ def bench_serve(args, mpr, torch, seconds: float):
                     "p50_ms": _lat_stats(res)["p50_ms"], "p99_ms": _lat_stats(res)["p99_ms"],
                     "warm": _lat_stats(res, lambda r: r["cold"] == 0), "ready_wait_s": build_s,
                     **_check(goldens, qs, res)})
-        b0 = S.stats()["batches"]
+        b0, sh0 = S.stats()["batches"], S.stats()["shared_reads"]
         res_b, sat = _closed_loop(serve, S, qs_burst, 600)
         sat.update(_check(goldens, qs_burst, res_b))
         sat["launches"] = S.stats()["batches"] - b0
+        # queries whose giant power another query of their launch streamed
+        sat["shared_reads"] = S.stats()["shared_reads"] - sh0
         sat["max_batch"] = S.stats()["max_batch_seen"]
         out["saturation"] = sat
         stats = S.stats()
@@ -1017,6 +1019,22 @@ def bench_serve(args, mpr, torch, seconds: float):
             per["same_answers_as_grouped"] = [r["gamma"] for r in res_p] == [r["gamma"] for r in res_b]
         out["per_instance"] = {"form": "one query per launch, one launch in flight (max_batch 1, slots 1)", **per}
         out["saturation"]["speedup_vs_per_instance"] = round(out["saturation"]["qps"] / per["qps"], 2)
+    if args.serve_period:
+        # Labelled fast mode: Proposition 8's shortcut, not the per-query path.
+        with serve.Server(max_n=1000, hbm_budget_bytes=budget, period_mode=True) as S:
+            build_s = {}
+            for m in range(3, 10):
+                t0 = time.perf_counter()
+                r = S.query(m, 1000)
+                build_s[m] = round(time.perf_counter() - t0, 3)
+                assert r["status"] == 0
+            res_t, tab = _closed_loop(serve, S, qs_burst, 600)
+            tab.update(_check(goldens, qs_burst, res_t))
+            tab["same_answers_as_grouped"] = [r["gamma"] for r in res_t] == [r["gamma"] for r in res_b]
+            st = S.stats()
+        out["period_mode"] = {"form": "labelled fast mode (Proposition 8): per m, one period search with "
+                                      "compressed-K steps up to n = 1000, then a table read per query",
+                              "build_s": build_s, "query_launches": st["batches"], **tab}
     return out
 
 
@@ -1045,6 +1063,8 @@ def main():
     ap.add_argument("--serve-cold-seconds", type=float, default=12.0,
                     help="length of the cold leg (fresh engine, no ladder built)")
     ap.add_argument("--serve-burst", type=int, default=20000, help="queries of the saturation legs")
+    ap.add_argument("--serve-period", type=int, default=1,
+                    help="1: also run the labelled period-table mode of the server on the same burst")
     ap.add_argument("--serve-per-instance", type=int, default=1)
     ap.add_argument("--legs", type=int, default=1, help="default run: also the compact config 1-4 legs")
     ap.add_argument("--config2-rows", type=int, default=48)

@@ -452,6 +452,17 @@ typedef struct {
                                  busy; a request is picked up without a thread
                                  wake-up); 0: it sleeps until a request or a
                                  launch needs it */
+    int period_mode;          /* 0: the per-query GPU path above.  1: the
+                                 labelled fast mode of Proposition 8: the
+                                 build of m searches the period of A
+                                 (compressed-K steps, 8 ring powers, up to
+                                 max_n) on its own host thread and stream,
+                                 keeps the traces of A^1..A^max_n on the host
+                                 (past the confirmed period, filled from it;
+                                 all computed when no period shows up to
+                                 max_n) and frees its device memory; a query
+                                 is a table read with no GPU work.  baby,
+                                 wide_only, max_batch and slots are unused. */
 } mpr_server_options;
 
 typedef struct {
@@ -468,6 +479,12 @@ typedef struct {
     int64_t submitted, completed, batches, max_batch_seen;
     int64_t builds, evictions, admission_waits, resident_bytes;
     int64_t narrow_builds;    /* finished builds whose queries read byte copies */
+    int64_t shared_reads;     /* queries answered without a read of their own of
+                                 the giant power: another query of the same
+                                 launch with the same m and i read it for both
+                                 (byte copies; groups of up to 8) */
+    int64_t period_answers;   /* queries answered from a period table
+                                 (period_mode) */
 } mpr_server_stats;
 
 /* Starts an engine with its own worker thread and two non-blocking HIP
@@ -477,7 +494,9 @@ typedef struct {
  * (1 <= j <= B) as the trace of A^(B i) (x) A^j (Corollary 7) without
  * forming the product: one pass reading both matrices along rows (as
  * mpr_trace_of_product_t), over byte copies of them unless wide_only is set
- * or an entry does not fit (canonical Roman powers have entries <= 2m).  The engine allocates its ladders itself,
+ * or an entry does not fit (canonical Roman powers have entries <= 2m).
+ * Queries of one launch on byte copies that share the giant power (same m
+ * and i) are answered in groups of up to 8 that stream it once.  The engine allocates its ladders itself,
  * within hbm_budget_bytes (least recently used idle ladders are evicted;
  * requests that do not fit wait).  *server_host receives an opaque handle. */
 mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host);
@@ -497,6 +516,10 @@ double mpr_server_now(void *server);
 /* Device bytes one ladder of m takes for the given baby step, max_n and
  * wide_only option. */
 int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n, int wide_only);
+/* Device bytes a period-mode build of m holds while it runs (A and the
+ * period search's workspace; none once the build ends); -1 for m outside
+ * 1..11. */
+int64_t mpr_server_period_bytes(int m);
 /* Stops the worker, waits for outstanding GPU work, frees everything. */
 mpr_status mpr_server_destroy(void *server);
 

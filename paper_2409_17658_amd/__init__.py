@@ -55,7 +55,7 @@ class ChainDesc(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("baby", ctypes.c_int), ("max_n", ctypes.c_int64),
                 ("max_batch", ctypes.c_int), ("slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("wide_only", ctypes.c_int), ("busy_poll", ctypes.c_int)]
+                ("wide_only", ctypes.c_int), ("busy_poll", ctypes.c_int), ("period_mode", ctypes.c_int)]
 
 
 class QueryResult(ctypes.Structure):
@@ -66,7 +66,8 @@ class QueryResult(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "batches", "max_batch_seen", "builds",
-                                             "evictions", "admission_waits", "resident_bytes", "narrow_builds")]
+                                             "evictions", "admission_waits", "resident_bytes", "narrow_builds",
+                                             "shared_reads", "period_answers")]
 
 
 _lib = None
@@ -126,6 +127,7 @@ _SIGS = {
     "mpr_server_stats_get": (_I, [_P, _P]),
     "mpr_server_now": (ctypes.c_double, [_P]),
     "mpr_server_ladder_bytes": (_I64, [_I, _I, _I64, _I]),
+    "mpr_server_period_bytes": (_I64, [_I]),
     "mpr_server_destroy": (_I, [_P]),
     "mpr_gemm_config_count": (_I, []),
     "mpr_gemm_config_info": (_I, [_I, _P, _P, _P, _P, _P, _P, _P]),

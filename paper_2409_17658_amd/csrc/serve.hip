@@ -17,14 +17,23 @@
 // ladder is admitted only if its bytes fit the HBM budget; idle ladders are
 // evicted least-recently-used to make room, and requests that do not fit
 // wait in an admission queue.
+//
+// The labelled fast mode (period_mode) answers from Proposition 8 instead:
+// the build of m searches the period of A (compressed-K chain, ring of
+// powers, class hashes) up to max_n on a host thread and stream of its own,
+// keeps the traces of A^1 .. A^max_n on the host (those past the confirmed
+// period filled from it) and releases its device memory; a query is then a
+// table read, with no GPU work.
 #include <string.h>
 #include <sys/prctl.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <string>
 #include <mutex>
 #include <thread>
@@ -52,14 +61,86 @@ struct TRDesc {
     const uint8_t *X8, *YT8;  // their byte copies, used when `narrow`
     int64_t n, ld, ld8, first_block;
     int vec, narrow;
+    int gpos, gsize;  // position in its group, and (at position 0) the group's size
 };
 
 // Blocks of one query of n x n operands.
 static inline int64_t trace_blocks(int64_t n) { return tr_blocks(n); }
 
-// One launch for all queries of a batch: query q owns the blocks
-// [first_block, first_block + trace_blocks(n)); each block takes TR_ROWS
-// rows of its query and folds their minimum into the query's result word.
+// Queries that share a giant power (same m and i) in one pass.
+constexpr int TR_GROUP = 8;
+
+// Rows [r0, r0 + TR_ROWS) of the nq <= TR_GROUP queries of a group, which
+// share X = A^(B i) and differ in YT (byte copies): wave w streams row r0 + w
+// of X once, and the same row of every YT_q beside it, so a group of q
+// queries reads X once instead of q times.  Query q's minimum is folded
+// into out[q].
+__device__ __forceinline__ void tr8_group_rows(const TRDesc *__restrict__ g, int nq, int64_t r0, int64_t *out)
+{
+    __shared__ int64_t red[TR_GROUP][TR_ROWS];
+    typedef const __attribute__((address_space(1))) uint8_t gbyte;
+    const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t n = g[0].n, ld8 = g[0].ld8, i = r0 + w;
+    if (i < n) {  // wave-uniform
+        gbyte *gx = (gbyte *)g[0].X8 + i * ld8;
+        u16x2 best[TR_GROUP];
+#pragma unroll
+        for (int q = 0; q < TR_GROUP; q++) best[q] = (u16x2){0xFFFF, 0xFFFF};
+        const int64_t n16 = n & ~(int64_t)15;
+        const uint4 inf = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        for (int64_t c = (int64_t)lane * 16; c < n16; c += TR_TRIP * 1024) {
+            uint4 a[TR_TRIP];
+#pragma unroll
+            for (int k = 0; k < TR_TRIP; k++)
+                a[k] = c + k * 1024 < n16 ? gload16((const gu16 *)(gx + c + k * 1024)) : inf;
+#pragma unroll
+            for (int q = 0; q < TR_GROUP; q++) {
+                if (q >= nq) break;  // uniform
+                gbyte *gy = (gbyte *)g[q].YT8 + i * ld8;
+                uint4 b[TR_TRIP];
+#pragma unroll
+                for (int k = 0; k < TR_TRIP; k++)
+                    b[k] = c + k * 1024 < n16 ? gload16((const gu16 *)(gy + c + k * 1024)) : inf;
+#pragma unroll
+                for (int k = 0; k < TR_TRIP; k++) best[q] = tr8_min16(a[k], b[k], best[q]);
+            }
+        }
+        const int64_t rx = g[0].RX ? g[0].RX[i] : 0;
+#pragma unroll
+        for (int q = 0; q < TR_GROUP; q++) {
+            if (q >= nq) break;
+            gbyte *gy = (gbyte *)g[q].YT8 + i * ld8;
+            uint32_t m = best[q].x < best[q].y ? best[q].x : best[q].y;
+            for (int64_t c = n16 + lane; c < n; c += 64) {
+                const uint32_t s = (uint32_t)gx[c] + (uint32_t)gy[c];
+                m = s < m ? s : m;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint32_t o = __shfl_xor(m, off, 64);
+                m = o < m ? o : m;
+            }
+            const int64_t cy = g[q].CY ? g[q].CY[i] : 0;
+            int64_t v = ROW_NONE;
+            if (m < 255u && rx != ROW_NONE && cy != ROW_NONE) v = rx + cy + (int64_t)m;
+            if (lane == 0) red[q][w] = v;
+        }
+    } else if ((threadIdx.x & 63) == 0) {
+        for (int q = 0; q < nq; q++) red[q][w] = ROW_NONE;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nq) {
+        int64_t v = red[threadIdx.x][0];
+        for (int k = 1; k < TR_ROWS; k++) v = red[threadIdx.x][k] < v ? red[threadIdx.x][k] : v;
+        tp_fold_min(&out[threadIdx.x], v);
+    }
+}
+
+// One launch for all queries of a batch.  Queries come in groups (the
+// queries of a group are consecutive and share the giant power; a group of
+// one otherwise); every query of a group carries the group's first block,
+// and the group owns the blocks [first_block, first_block +
+// trace_blocks(n)); each block takes TR_ROWS rows of its group and folds
+// their minima into the queries' result words.
 __global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *__restrict__ d, int nq, int64_t *out)
 {
     const int64_t b = blockIdx.x;
@@ -71,11 +152,17 @@ __global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *_
         else
             hi = mid - 1;
     }
-    const TRDesc q = d[lo];
+    TRDesc q = d[lo];
+    int lead = lo;
+    if (q.gpos != 0) {  // a member of a group: its leader carries the group
+        lead = lo - q.gpos;
+        q = d[lead];
+    }
+    const int64_t r0 = (b - q.first_block) * TR_ROWS;
     if (q.narrow)  // block-uniform
-        tr8_rows(q.X8, q.RX, q.YT8, q.CY, q.n, q.ld8, (b - q.first_block) * TR_ROWS, true, &out[lo]);
+        tr8_group_rows(&d[lead], q.gsize, r0, &out[lead]);
     else
-        tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, (b - q.first_block) * TR_ROWS, q.vec != 0, &out[lo]);
+        tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, r0, q.vec != 0, &out[lead]);
 }
 
 // Byte copy of an n x n canonical power (0xFFFF -> 0xFF), one row per
@@ -126,6 +213,14 @@ __global__ void fill_none_kernel(int64_t *p, int count)
 // ------------------------------------------------------------ engine
 using Clock = std::chrono::steady_clock;
 
+// A period-mode build in flight: its thread writes the fields, then `done`.
+struct PeriodBuild {
+    std::thread th;
+    std::atomic<bool> done{false};
+    mpr_status status = MPR_OK;
+    std::vector<int64_t> traces;  // [k] = trace of A^k, k = 1..max_n
+};
+
 struct Ladder {
     int m = 0;
     int64_t n = 0, ld = 0;
@@ -146,6 +241,9 @@ struct Ladder {
     int inflight = 0;
     double last_use = 0;
     double build_s0 = 0, build_s = 0;
+    bool period = false;                  // period mode: answers from `table`
+    std::shared_ptr<PeriodBuild> pb;      // the build, while it runs
+    std::vector<int64_t> table;           // period mode: [n] = gamma_R(P_m x C_n)
 };
 
 struct Request {
@@ -214,6 +312,74 @@ static size_t ladder_bytes(int m, int B, int G, bool bytes8, int64_t *n_out, int
 }
 
 static int giant_count(const mpr_server_options &o) { return (int)((o.max_n - 1) / o.baby); }
+
+// Ring powers of a period-mode search: confirms periods up to 7.
+constexpr int kPeriodSlots = 8;
+constexpr int kPeriodFlags = MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND;
+
+// Device bytes of a period-mode build of m: A, then the search's workspace
+// (sized with a compressed-K plan for a dense A, since the bytes are
+// admitted before A exists; the search sizes the plan for A itself and
+// gives the rest to its ring).  Released when the build ends.
+static size_t period_build_bytes(int m, int64_t *n_out, int64_t *ld_out)
+{
+    const int64_t n = transfer_size(m), ld = round_up(n, 8);
+    size_t ws = 0;
+    if (mpr_period_workspace_size_ex(n, kPeriodSlots, kPeriodFlags, &ws) != MPR_OK) return SIZE_MAX;
+    if (n_out) *n_out = n;
+    if (ld_out) *ld_out = ld;
+    return (size_t)round_up(n * ld * 2, 256) + ws;
+}
+
+// Device bytes a build of m takes in this server's mode.
+static size_t build_bytes(const Server &S, int m)
+{
+    if (S.opt.period_mode) return period_build_bytes(m, nullptr, nullptr);
+    return ladder_bytes(m, S.opt.baby, giant_count(S.opt), !S.opt.wide_only, nullptr, nullptr);
+}
+
+// Starts a period-mode build of L.m on its own thread and stream.
+static mpr_status start_period_build(Server &S, Ladder &L)
+{
+    L.bytes = period_build_bytes(L.m, &L.n, &L.ld);
+    if (L.bytes == SIZE_MAX) return MPR_EINVAL;
+    if (hipMalloc(&L.mem, L.bytes) != hipSuccess) return MPR_ENOMEM;
+    auto pb = std::make_shared<PeriodBuild>();
+    pb->traces.assign((size_t)S.opt.max_n + 1, ROW_NONE);
+    const int dev = S.device, m = L.m;
+    const int64_t n = L.n, ld = L.ld, kmax = S.opt.max_n;
+    char *mem = (char *)L.mem;
+    const size_t bytes = L.bytes, mat = (size_t)round_up(n * ld * 2, 256);
+    PeriodBuild *b = pb.get();  // owned by the ladder until the worker joins the thread
+    try {
+        pb->th = std::thread([b, dev, m, n, ld, kmax, mem, bytes, mat]() {
+            mpr_status e = hipSetDevice(dev) == hipSuccess ? MPR_OK : MPR_EHIP;
+            hipStream_t s = nullptr;
+            if (e == MPR_OK && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) e = MPR_EHIP;
+            if (e == MPR_OK) e = transfer_launch(m, (u16 *)mem, ld, s);
+            int64_t mu = 0, lam = 0, c = 0;
+            if (e == MPR_OK)
+                e = mpr_find_period_ex((const uint16_t *)mem, n, ld, kmax, kPeriodFlags, &mu, &lam, &c,
+                                       b->traces.data(), mem + mat, bytes - mat, (mpr_stream)s);
+            if (e == MPR_ENOTFOUND) e = MPR_OK;  // no repeat up to max_n: every trace was computed directly
+            if (s) {
+                if (hipStreamSynchronize(s) != hipSuccess && e == MPR_OK) e = MPR_EHIP;
+                (void)hipStreamDestroy(s);
+            }
+            b->status = e;
+            b->done.store(true, std::memory_order_release);
+        });
+    } catch (...) {
+        return MPR_EHIP;
+    }
+    L.pb = pb;
+    L.period = true;
+    L.state = Ladder::BUILDING;
+    L.build_s0 = S.now();
+    S.resident += L.bytes;
+    stats_update(S, [](mpr_server_stats &t) { t.builds++; });
+    return MPR_OK;
+}
 
 // Enqueues the whole ladder build on the build stream.
 static mpr_status start_build(Server &S, Ladder &L)
@@ -320,6 +486,7 @@ static mpr_status start_build(Server &S, Ladder &L)
 
 static void free_ladder(Server &S, Ladder &L)
 {
+    if (L.pb && L.pb->th.joinable()) L.pb->th.join();  // a period-mode build still running
     if (L.ready) (void)hipEventDestroy(L.ready);
     if (L.mem) (void)hipFree(L.mem);
     S.resident -= L.bytes;
@@ -364,8 +531,7 @@ constexpr size_t kFreeMargin = (size_t)256 << 20;
 // must wait for memory that a running build or query will release.
 static bool admit(Server &S, int m)
 {
-    const int B = S.opt.baby, G = giant_count(S.opt);
-    const size_t need = ladder_bytes(m, B, G, !S.opt.wide_only, nullptr, nullptr);
+    const size_t need = build_bytes(S, m);
     if (need > S.opt.hbm_budget_bytes) return false;
     for (;;) {
         const bool budget_ok = S.resident + need <= S.opt.hbm_budget_bytes;
@@ -376,7 +542,8 @@ static bool admit(Server &S, int m)
         for (auto &kv : S.ladders) {
             Ladder &L = kv.second;
             busy |= L.state == Ladder::BUILDING || (L.state == Ladder::READY && L.inflight > 0);
-            if (L.state != Ladder::READY || L.inflight > 0 || !S.waiting[kv.first].empty()) continue;
+            if (L.state != Ladder::READY || L.inflight > 0 || !S.waiting[kv.first].empty() || L.bytes == 0)
+                continue;  // (a period-mode table holds no device memory)
             if (!victim || L.last_use < victim->last_use) victim = &L;
         }
         if (victim) {
@@ -396,7 +563,7 @@ static bool admit(Server &S, int m)
     }
     Ladder &L = S.ladders[m];
     L.m = m;
-    const mpr_status e = start_build(S, L);
+    const mpr_status e = S.opt.period_mode ? start_period_build(S, L) : start_build(S, L);
     if (e != MPR_OK) {
         if (L.mem) {
             (void)hipStreamSynchronize(S.bstream);  // part of the build may be enqueued
@@ -463,7 +630,30 @@ static void worker_main(Server *Sp)
         // 2. builds that finished
         for (auto &kv : S.ladders) {
             Ladder &L = kv.second;
-            if (L.state != Ladder::BUILDING || hipEventQuery(L.ready) != hipSuccess) continue;
+            if (L.state != Ladder::BUILDING || !L.period) continue;
+            if (!L.pb->done.load(std::memory_order_acquire)) continue;
+            L.pb->th.join();
+            const mpr_status st = L.pb->status;
+            L.build_s = S.now() - L.build_s0;
+            L.last_use = S.now();
+            if (st == MPR_OK) {
+                L.table = std::move(L.pb->traces);
+                L.pb.reset();
+                (void)hipFree(L.mem);  // the table is all a period-mode query reads
+                L.mem = nullptr;
+                S.resident -= L.bytes;
+                L.bytes = 0;
+                L.state = Ladder::READY;
+            } else {
+                free_ladder(S, L);
+                L.m = kv.first;
+                L.state = Ladder::FAILED;
+                L.fail_status = st;
+            }
+        }
+        for (auto &kv : S.ladders) {
+            Ladder &L = kv.second;
+            if (L.state != Ladder::BUILDING || L.period || hipEventQuery(L.ready) != hipSuccess) continue;
             int32_t st = 0, wide = 1;
             L.baby_trace.assign(B + 1, ROW_NONE);
             if (hipMemcpy(&st, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -489,7 +679,7 @@ static void worker_main(Server *Sp)
                 complete(S, r, ROW_NONE, MPR_EINVAL, S.now());
                 continue;
             }
-            if (ladder_bytes(r.m, B, giant_count(S.opt), !S.opt.wide_only, nullptr, nullptr) > S.opt.hbm_budget_bytes) {
+            if (build_bytes(S, r.m) > S.opt.hbm_budget_bytes) {
                 complete(S, r, ROW_NONE, MPR_ENOMEM, S.now());  // could never be admitted
                 continue;
             }
@@ -536,6 +726,13 @@ static void worker_main(Server *Sp)
             }
             if (L.state != Ladder::READY) continue;
             auto &dq = kv.second;
+            if (L.period) {  // the labelled fast mode: a table read per query
+                const int64_t cnt = (int64_t)dq.size();
+                for (; !dq.empty(); dq.pop_front()) complete(S, dq.front(), L.table[dq.front().n], MPR_OK, S.now());
+                L.last_use = S.now();
+                if (cnt) stats_update(S, [cnt](mpr_server_stats &t) { t.period_answers += cnt; });
+                continue;
+            }
             while (!dq.empty()) {
                 Request r = dq.front();
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
@@ -553,15 +750,32 @@ static void worker_main(Server *Sp)
             }
         }
         if (slot && !batch.empty()) {
-            int64_t blocks = 0;
+            // Queries on byte copies that share a giant power (same m and i)
+            // go in groups of up to TR_GROUP, which read it once; the order
+            // of the batch follows the groups.
+            std::stable_sort(batch.begin(), batch.end(), [B](const Request &x, const Request &y) {
+                const int64_t ix = (x.n - 1) / B, iy = (y.n - 1) / B;
+                return x.m != y.m ? x.m < y.m : ix < iy;
+            });
+            int64_t blocks = 0, shared = 0;
+            int lead = 0;
             for (size_t q = 0; q < batch.size(); q++) {
                 const Request &r = batch[q];
                 Ladder &L = S.ladders[r.m];
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
                 const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
+                const TRDesc &head = slot->desc_host[lead];  // of the group the query may join
+                const bool join = q > 0 && L.narrow && head.narrow && head.X8 == L.Ng8[i] && head.gsize < TR_GROUP;
+                if (!join) lead = (int)q;
+                const int64_t first = join ? head.first_block : blocks;
                 slot->desc_host[q] = TRDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.Ng8[i], L.Nb8[j],
-                                            L.n,     L.ld,     L.ld8,    blocks,   vec,      L.narrow ? 1 : 0};
-                blocks += trace_blocks(L.n);
+                                            L.n,     L.ld,     L.ld8,    first,    vec,      L.narrow ? 1 : 0,
+                                            (int)q - lead, 1};
+                if (join) {
+                    slot->desc_host[lead].gsize++;
+                    shared++;
+                } else
+                    blocks += trace_blocks(L.n);
                 L.inflight++;
                 L.last_use = S.now();
             }
@@ -586,8 +800,9 @@ static void worker_main(Server *Sp)
             slot->reqs = batch;
             slot->busy = true;
             slot->t_launch = S.now();
-            stats_update(S, [nq](mpr_server_stats &t) {
+            stats_update(S, [nq, shared](mpr_server_stats &t) {
                 t.batches++;
+                t.shared_reads += shared;
                 t.max_batch_seen = std::max<int64_t>(t.max_batch_seen, nq);
             });
         }
@@ -684,6 +899,13 @@ extern "C" int64_t mpr_server_ladder_bytes(int m, int baby, int64_t max_n, int w
 {
     if (m < 1 || m > 11 || baby < 1 || max_n < 3) return -1;
     return (int64_t)ladder_bytes(m, baby, (int)((max_n - 1) / baby), wide_only == 0, nullptr, nullptr);
+}
+
+extern "C" int64_t mpr_server_period_bytes(int m)
+{
+    if (m < 1 || m > 11) return -1;
+    const size_t b = period_build_bytes(m, nullptr, nullptr);
+    return b == SIZE_MAX ? -1 : (int64_t)b;
 }
 
 extern "C" mpr_status mpr_server_destroy(void *server)

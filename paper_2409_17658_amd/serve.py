@@ -16,9 +16,9 @@ from . import MprError, QueryResult, ServerOptions, ServerStats, lib
 class Server:
     def __init__(self, device: int = 0, baby: int = 32, max_n: int = 1000, max_batch: int = 256,
                  slots: int = 4, hbm_budget_bytes: int = 200 << 30, wide_only: bool = False,
-                 busy_poll: bool = False):
+                 busy_poll: bool = False, period_mode: bool = False):
         self.opt = ServerOptions(device, baby, max_n, max_batch, slots, hbm_budget_bytes, int(bool(wide_only)),
-                                 int(bool(busy_poll)))
+                                 int(bool(busy_poll)), int(bool(period_mode)))
         h = ctypes.c_void_p()
         st = lib().mpr_server_create(ctypes.byref(self.opt), ctypes.byref(h))
         if st != 0:
@@ -85,6 +85,11 @@ class Server:
 
 def ladder_bytes(m: int, baby: int = 32, max_n: int = 1000, wide_only: bool = False) -> int:
     return int(lib().mpr_server_ladder_bytes(m, baby, max_n, int(bool(wide_only))))
+
+
+def period_build_bytes(m: int) -> int:
+    """Device bytes a period-mode build of m holds while it runs."""
+    return int(lib().mpr_server_period_bytes(m))
 
 
 def run_open_loop(server: Server, arrivals, timeout_s: float = 600.0):

@@ -139,10 +139,39 @@ def test_server_large_ladders_mixed_batches(serve, wide_only):
     assert st["narrow_builds"] == (0 if wide_only else 2)
 
 
+def test_server_shared_giant_groups(serve):
+    """Queries of one launch that share a giant power A^(32 i) are answered in
+    groups of up to 8 that read it once.  A burst submitted while the ladders
+    of m = 7 and m = 8 (N = 2507, 7411) are still being built, so each
+    ladder's queries are ready together and go in one launch: 20 queries on
+    A^160 of m = 8 (groups of 8, 8, 4), 10 on A^288 of m = 7 (8, 2) and four
+    alone; every answer equal to its answer alone and to the stored tables."""
+    qs = [(8, 160 + j) for j in range(1, 21)] + [(7, 288 + j) for j in range(3, 31, 3)]
+    qs += [(8, 999), (7, 40), (8, 100), (7, 641)]
+    rng = np.random.default_rng(23)
+    qs = [qs[k] for k in rng.permutation(len(qs))]
+    with serve.Server(baby=32, max_n=1000, max_batch=256, slots=1, hbm_budget_bytes=32 << 30) as S:
+        for k, (m, n) in enumerate(qs):
+            S.submit(m, n, k)
+        got, t_end = {}, time.monotonic() + 240
+        while len(got) < len(qs) and time.monotonic() < t_end:
+            for r in S.poll(50):
+                got[r["tag"]] = r
+        st = S.stats()
+        alone = {q: S.query(*q)["gamma"] for q in set(qs)}
+        st1 = S.stats()
+    assert len(got) == len(qs)
+    for k, (m, n) in enumerate(qs):
+        assert got[k]["status"] == 0 and got[k]["cold"] == 1
+        assert got[k]["gamma"] == alone[(m, n)] == golden_gamma(m, n), (m, n)
+    assert st["narrow_builds"] == 2
+    assert st["shared_reads"] == (7 + 7 + 3) + (7 + 1)
+    assert st1["shared_reads"] == st["shared_reads"]  # one query per launch
+
+
 def test_server_large_batches(serve):
-    """One launch slot and a burst of 200 queries: batches grow past the 16
-    queries whose descriptors travel in the launch arguments, so both launch
-    forms run; every answer against the oracle."""
+    """One launch slot and a burst of 200 queries: batches grow past 16
+    queries; every answer against the oracle."""
     rng = np.random.default_rng(17)
     qs = [(int(m), int(n)) for m, n in zip(rng.integers(3, 7, 200), rng.integers(3, 201, 200))]
     with serve.Server(baby=16, max_n=200, max_batch=256, slots=1, hbm_budget_bytes=8 << 30) as S:
@@ -245,3 +274,46 @@ def test_build_refused_without_free_memory_then_retried(serve):
     assert r2["status"] == 0 and r2["gamma"] == oracle_gamma(4, 21)
     assert r3["status"] == 0 and r3["gamma"] == oracle_gamma(3, 11)
     assert st["evictions"] >= 1
+
+
+def test_server_period_mode(serve):
+    """The labelled fast mode (Proposition 8): each build searches the period
+    of A up to max_n and keeps the traces, so a query is a table read (no
+    query launch, no resident device memory); every answer equals the
+    stored tables (m = 9: Section 4.3's closed form), including n past the
+    confirmed period, whose traces come from the period."""
+    ns = (3, 4, 5, 17, 31, 32, 33, 100, 299, 641, 999, 1000)
+    qs = [(m, n) for m in range(3, 10) for n in ns]
+    with serve.Server(max_n=1000, hbm_budget_bytes=64 << 30, period_mode=True) as S:
+        for k, (m, n) in enumerate(qs):
+            S.submit(m, n, k)
+        got, t_end = {}, time.monotonic() + 240
+        while len(got) < len(qs) and time.monotonic() < t_end:
+            for r in S.poll(50):
+                got[r["tag"]] = r
+        again = S.query(8, 777)
+        bad = S.query(8, 1001)  # past max_n
+        st = S.stats()
+    assert len(got) == len(qs)
+    for k, (m, n) in enumerate(qs):
+        exp = (4 * n if n % 5 == 0 else 4 * n + 2) if m == 9 else golden_gamma(m, n)
+        assert got[k]["status"] == 0 and got[k]["gamma"] == exp, (m, n)
+    assert again["status"] == 0 and again["cold"] == 0 and again["gamma"] == golden_gamma(8, 777)
+    assert bad["status"] == 1  # MPR_EINVAL
+    assert st["builds"] == 7 and st["batches"] == 0 and st["resident_bytes"] == 0
+    assert st["period_answers"] == len(qs) + 1
+
+
+def test_server_period_mode_budget(serve):
+    """Period mode admits a build by its transient bytes: a budget below
+    them answers MPR_ENOMEM; one above, after which the bytes are released."""
+    need = serve.period_build_bytes(7)
+    assert need > 0
+    with serve.Server(max_n=300, hbm_budget_bytes=need - 1, period_mode=True) as S:
+        r = S.query(7, 100)
+    assert r["status"] == 2  # MPR_ENOMEM: could never be admitted
+    with serve.Server(max_n=300, hbm_budget_bytes=need, period_mode=True) as S:
+        r = S.query(7, 100)
+        st = S.stats()
+    assert r["status"] == 0 and r["gamma"] == golden_gamma(7, 100)
+    assert st["resident_bytes"] == 0 and st["builds"] == 1
