@@ -101,91 +101,30 @@ __device__ __forceinline__ void tr_rows(const u16 *__restrict__ X, const int64_t
 // Entries 0..TR8_FMAX are finite, 0xFF is infinity; no other value occurs
 // (the producer checks it).  A finite sum is then at most 2 TR8_FMAX = 254
 // and any sum with an infinite operand is at least 255, so a packed uint16
-// add and min need no test per term: bytes are spread into uint16 pairs,
-// added and folded into a running uint16-pair minimum.
+// add and min need no test per term: the even bytes (0, 2) and the odd
+// bytes (1, 3) of a word are taken as two uint16 pairs (a byte sum is at
+// most 510 and never carries into the next half), added, and folded into a
+// running uint16-pair minimum.
 constexpr uint32_t TR8_FMAX = 127;
 
-__device__ __forceinline__ u16x2 tr8_lo(uint32_t w)  // bytes 0, 1
-{
-    return __builtin_bit_cast(u16x2, (w & 0xFFu) | ((w << 8) & 0xFF0000u));
-}
-__device__ __forceinline__ u16x2 tr8_hi(uint32_t w)  // bytes 2, 3
-{
-    return __builtin_bit_cast(u16x2, ((w >> 16) & 0xFFu) | ((w >> 8) & 0xFF0000u));
-}
+__device__ __forceinline__ u16x2 tr8_even(uint32_t w) { return __builtin_bit_cast(u16x2, w & 0x00FF00FFu); }
+__device__ __forceinline__ u16x2 tr8_odd(uint32_t w) { return __builtin_bit_cast(u16x2, (w >> 8) & 0x00FF00FFu); }
 
-// 16 positions of two 16-byte chunks.
+// 16 positions of two 16-byte chunks: the eight sums first, then their
+// minima (a packed min reading the packed add issued just before it waits
+// a cycle).
 __device__ __forceinline__ u16x2 tr8_min16(uint4 a, uint4 b, u16x2 best)
 {
     const uint32_t xa[4] = {a.x, a.y, a.z, a.w}, yb[4] = {b.x, b.y, b.z, b.w};
+    u16x2 s[8];
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        best = __builtin_elementwise_min(best, tr8_lo(xa[q]) + tr8_lo(yb[q]));
-        best = __builtin_elementwise_min(best, tr8_hi(xa[q]) + tr8_hi(yb[q]));
+        s[2 * q] = tr8_even(xa[q]) + tr8_even(yb[q]);
+        s[2 * q + 1] = tr8_odd(xa[q]) + tr8_odd(yb[q]);
     }
+#pragma unroll
+    for (int q = 0; q < 8; q++) best = __builtin_elementwise_min(best, s[q]);
     return best;
-}
-
-// Wave-wide min over l < n of x[l] + y[l] for one row of bytes (TR_NONE when
-// every term has an infinite operand), returned to every lane.  `vec`: both
-// rows 16-byte aligned.  Trips as in tr_row_min (a chunk past the row's end
-// reads as 0xFF bytes, infinite).
-__device__ __forceinline__ uint32_t tr8_row_min(const uint8_t *x, const uint8_t *y, int64_t n, bool vec)
-{
-    const int lane = (int)(threadIdx.x & 63);
-    const __attribute__((address_space(1))) uint8_t *gx = (const __attribute__((address_space(1))) uint8_t *)x;
-    const __attribute__((address_space(1))) uint8_t *gy = (const __attribute__((address_space(1))) uint8_t *)y;
-    u16x2 best = {0xFFFF, 0xFFFF};
-    int64_t tail = 0;
-    if (vec) {
-        const int64_t n16 = n & ~(int64_t)15;
-        const uint4 inf = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-        for (int64_t c = (int64_t)lane * 16; c < n16; c += TR_TRIP * 1024) {  // chunks c, c + 1024, ...
-            uint4 a[TR_TRIP], b[TR_TRIP];
-#pragma unroll
-            for (int q = 0; q < TR_TRIP; q++) {
-                const bool in = c + q * 1024 < n16;
-                a[q] = in ? gload16((const gu16 *)(gx + c + q * 1024)) : inf;
-                b[q] = in ? gload16((const gu16 *)(gy + c + q * 1024)) : inf;
-            }
-#pragma unroll
-            for (int q = 0; q < TR_TRIP; q++) best = tr8_min16(a[q], b[q], best);
-        }
-        tail = n16;
-    }
-    uint32_t m = best.x < best.y ? best.x : best.y;
-    for (int64_t c = tail + lane; c < n; c += 64) {
-        const uint32_t s = (uint32_t)gx[c] + (uint32_t)gy[c];
-        m = s < m ? s : m;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t o = __shfl_xor(m, off, 64);
-        m = o < m ? o : m;
-    }
-    return m >= 255u ? TR_NONE : m;
-}
-
-// tr_rows over byte copies (row stride ld8 bytes).
-__device__ __forceinline__ void tr8_rows(const uint8_t *__restrict__ X, const int64_t *__restrict__ RX,
-                                         const uint8_t *__restrict__ YT, const int64_t *__restrict__ CY, int64_t n,
-                                         int64_t ld8, int64_t r0, bool vec, int64_t *out)
-{
-    __shared__ int64_t red[TR_ROWS];
-    const int w = (int)(threadIdx.x >> 6);
-    const int64_t i = r0 + w;
-    int64_t best = ROW_NONE;
-    if (i < n) {  // wave-uniform
-        const int64_t rx = RX ? RX[i] : 0, cy = CY ? CY[i] : 0;
-        const uint32_t m = tr8_row_min(X + i * ld8, YT + i * ld8, n, vec);
-        if (m != TR_NONE && rx != ROW_NONE && cy != ROW_NONE) best = rx + cy + (int64_t)m;
-    }
-    if ((threadIdx.x & 63) == 0) red[w] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t v = red[0];
-        for (int q = 1; q < TR_ROWS; q++) v = red[q] < v ? red[q] : v;
-        tp_fold_min(out, v);
-    }
 }
 
 // Launches the pass over all n rows (rowops.hip); *out is set first.
