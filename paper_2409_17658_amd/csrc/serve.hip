@@ -70,6 +70,16 @@ static inline int64_t trace_blocks(int64_t n) { return tr_blocks(n); }
 // Queries that share a giant power (same m and i) in one pass.
 constexpr int TR_GROUP = 8;
 
+// Result words of a launch.  Folding thousands of block minima into one
+// 64-bit word serialises them on its cache line at the memory side (a
+// relaxed agent-scope load, and an atomic when it lowers the word): at
+// m = 8 that cost about a sixth of the pass.  Block b folds into slot
+// b % TR_SLOTS instead, and query q's slot s is the word s * nqpad + q with
+// nqpad a multiple of 16, so the slots of one query lie on distinct 128-byte
+// lines; the host takes the minimum over the slots.
+constexpr int TR_SLOTS = 32;
+static inline int64_t slot_pitch(int64_t nq) { return (nq + 15) / 16 * 16; }
+
 // Rows [r0, r0 + TR_ROWS) of the nq <= TR_GROUP queries of a group, which
 // share X = A^(B i) and differ in YT (byte copies): wave w streams row r0 + w
 // of X once, and the same row of every YT_q beside it, so a group of q
@@ -140,8 +150,9 @@ __device__ __forceinline__ void tr8_group_rows(const TRDesc *__restrict__ g, int
 // one otherwise); every query of a group carries the group's first block,
 // and the group owns the blocks [first_block, first_block +
 // trace_blocks(n)); each block takes TR_ROWS rows of its group and folds
-// their minima into the queries' result words.
-__global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *__restrict__ d, int nq, int64_t *out)
+// their minima into the queries' words of its result slot.
+__global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *__restrict__ d, int nq,
+                                                                   int64_t nqpad, int64_t *out)
 {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nq - 1;  // last q with first_block <= b (every thread, same answer)
@@ -159,10 +170,11 @@ __global__ __launch_bounds__(256) void grouped_trace_rows_kernel(const TRDesc *_
         q = d[lead];
     }
     const int64_t r0 = (b - q.first_block) * TR_ROWS;
+    int64_t *o = out + (b % TR_SLOTS) * nqpad + lead;
     if (q.narrow)  // block-uniform
-        tr8_group_rows(&d[lead], q.gsize, r0, &out[lead]);
+        tr8_group_rows(&d[lead], q.gsize, r0, o);
     else
-        tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, r0, q.vec != 0, &out[lead]);
+        tr_rows(q.X, q.RX, q.YT, q.CY, q.n, q.ld, r0, q.vec != 0, o);
 }
 
 // Byte copy of an n x n canonical power (0xFFFF -> 0xFF), one row per
@@ -618,11 +630,14 @@ static void worker_main(Server *Sp)
         // 1. retire finished batches
         for (auto &sl : S.slots) {
             if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
+            const int64_t pitch = slot_pitch((int64_t)sl.reqs.size());
             for (size_t q = 0; q < sl.reqs.size(); q++) {
                 const Request &r = sl.reqs[q];
                 Ladder &L = S.ladders[r.m];
                 L.inflight--;
-                complete(S, r, sl.out_host[q], MPR_OK, sl.t_launch);
+                int64_t g = ROW_NONE;
+                for (int k = 0; k < TR_SLOTS; k++) g = std::min(g, sl.out_host[k * pitch + (int64_t)q]);
+                complete(S, r, g, MPR_OK, sl.t_launch);
             }
             sl.reqs.clear();
             sl.busy = false;
@@ -783,11 +798,14 @@ static void worker_main(Server *Sp)
             hipStream_t s = S.qstream;
             bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TRDesc) * nq, hipMemcpyHostToDevice,
                                      s) == hipSuccess;
-            hipLaunchKernelGGL(fill_none_kernel, dim3((nq + 255) / 256), dim3(256), 0, s, slot->out_dev, nq);
+            const int64_t pitch = slot_pitch(nq);
+            const int words = (int)(TR_SLOTS * pitch);
+            hipLaunchKernelGGL(fill_none_kernel, dim3((words + 255) / 256), dim3(256), 0, s, slot->out_dev, words);
             hipLaunchKernelGGL(grouped_trace_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
-                               nq, slot->out_dev);
+                               nq, pitch, slot->out_dev);
             ok = ok && hipGetLastError() == hipSuccess;
-            ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * nq, hipMemcpyDeviceToHost, s) == hipSuccess;
+            ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * (size_t)words, hipMemcpyDeviceToHost, s) ==
+                           hipSuccess;
             ok = ok && hipEventRecord(slot->done, s) == hipSuccess;
             if (!ok) {
                 S.fatal = "launch failed";
@@ -833,9 +851,10 @@ extern "C" mpr_status mpr_server_create(const mpr_server_options *opt, void **se
     for (auto &sl : S->slots) {
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&sl.desc_host, sizeof(TRDesc) * opt->max_batch) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&sl.out_host, 8 * opt->max_batch) == hipSuccess;
+        const size_t words = (size_t)TR_SLOTS * (size_t)slot_pitch(opt->max_batch);
+        ok = ok && hipHostMalloc((void **)&sl.out_host, 8 * words) == hipSuccess;
         ok = ok && hipMalloc((void **)&sl.desc_dev, sizeof(TRDesc) * opt->max_batch) == hipSuccess;
-        ok = ok && hipMalloc((void **)&sl.out_dev, 8 * opt->max_batch) == hipSuccess;
+        ok = ok && hipMalloc((void **)&sl.out_dev, 8 * words) == hipSuccess;
     }
     if (!ok) {
         mpr_server_destroy(S);
