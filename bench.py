@@ -1057,7 +1057,7 @@ def main():
     ap.add_argument("--probe", type=int, default=1, help="measure the VALU rate of both instruction mixes")
     ap.add_argument("--probe-iters", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson query stream in the default run (0: none)")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-cold-seconds", type=float, default=12.0,
