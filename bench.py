@@ -948,6 +948,15 @@ def _closed_loop(serve, S, qs, timeout_s):
                  **{k: v for k, v in _lat_stats(res).items() if k != "count"}}
 
 
+def _wait_built(S, count, timeout_s=120.0):
+    """Waits until `count` ladder builds have finished (the last giant of a
+    ladder answers queries just before its build is marked finished; the
+    Roman ladders are kept as byte copies, counted by narrow_builds)."""
+    t_end = time.monotonic() + timeout_s
+    while S.stats()["narrow_builds"] < count and time.monotonic() < t_end:
+        time.sleep(0.002)
+
+
 def bench_serve(args, mpr, torch, seconds: float):
     """Config 5 (m uniform in 3..9, n uniform in 3..1000; answers checked
     against the stored goldens, m = 9 against Section 4.3's closed form):
@@ -976,13 +985,15 @@ def bench_serve(args, mpr, torch, seconds: float):
             m9 = [r for r in cold if r["m"] == 9]
             # warm answers that completed while the m = 9 ladder was building
             overlap = 0
-            if m9:
-                b0, b1 = min(r["t_submit"] for r in m9), min(r["t_done"] for r in m9)
+            if m9:  # from the first m = 9 request to the last cold m = 9 answer (the build's end)
+                b0, b1 = min(r["t_submit"] for r in m9), max(r["t_done"] for r in m9)
                 overlap = sum(1 for r in res if r["cold"] == 0 and r["t_submit"] >= b0 and r["t_done"] <= b1)
             out["cold_leg"] = {"queries": len(res), "seconds": args.serve_cold_seconds,
                                "cold": _lat_stats(res, lambda r: r["cold"] == 1),
                                "warm": _lat_stats(res, lambda r: r["cold"] == 0),
                                "warm_answered_during_m9_build": overlap,
+                               # answered while their ladder was still being built
+                               "answered_from_building_ladders": S.stats()["early_answers"],
                                "m9_build_wait_s": round(max(r["t_done"] - r["t_submit"] for r in m9), 3) if m9 else None,
                                **_check(goldens, qs_cold, res)}
         build_s = {}
@@ -991,6 +1002,7 @@ def bench_serve(args, mpr, torch, seconds: float):
             r = S.query(m, 1000)
             build_s[m] = round(time.perf_counter() - t0, 3)
             assert r["status"] == 0
+        _wait_built(S, 7)
         t0 = time.perf_counter()
         res = serve.run_open_loop(S, qs, timeout_s=seconds * 4 + 600)
         wall = time.perf_counter() - t0
@@ -1014,6 +1026,7 @@ def bench_serve(args, mpr, torch, seconds: float):
         with serve.Server(baby=32, max_n=1000, max_batch=1, slots=1, hbm_budget_bytes=budget) as S:
             for m in range(3, 10):
                 assert S.query(m, 1000)["status"] == 0
+            _wait_built(S, 7)
             res_p, per = _closed_loop(serve, S, qs_burst, 600)
             per.update(_check(goldens, qs_burst, res_p))
             per["same_answers_as_grouped"] = [r["gamma"] for r in res_p] == [r["gamma"] for r in res_b]

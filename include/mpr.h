@@ -442,7 +442,9 @@ typedef struct {
     int baby;                 /* B: baby steps A^1..A^B, giant steps A^(B i) */
     int64_t max_n;            /* largest n served (n >= 3) */
     int max_batch;            /* most queries in one grouped launch */
-    int slots;                /* grouped launches in flight (1..64) */
+    int slots;                /* grouped launches in flight (1..64), plus one
+                                 on a stream of its own for queries of
+                                 ladders still being built */
     size_t hbm_budget_bytes;  /* ladders are admitted only within this */
     int wide_only;            /* 0: keep byte copies of the ladder powers and
                                  answer from them when every finite entry is
@@ -485,6 +487,8 @@ typedef struct {
                                  (byte copies; groups of up to 8) */
     int64_t period_answers;   /* queries answered from a period table
                                  (period_mode) */
+    int64_t early_answers;    /* queries answered from a ladder still being
+                                 built (its giants up to theirs written) */
 } mpr_server_stats;
 
 /* Starts an engine with its own worker thread and two non-blocking HIP

@@ -67,7 +67,7 @@ class QueryResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "batches", "max_batch_seen", "builds",
                                              "evictions", "admission_waits", "resident_bytes", "narrow_builds",
-                                             "shared_reads", "period_answers")]
+                                             "shared_reads", "period_answers", "early_answers")]
 
 
 _lib = None

@@ -248,6 +248,14 @@ struct Ladder {
     bool narrow = false;              // queries read the byte copies
     std::vector<int64_t> baby_trace;  // host, index j = 1..B
     hipEvent_t ready = nullptr;
+    // Progressive readiness while the ladder builds: step_ev[i] (i = 1..G)
+    // completes once the babies, their traces and the giants A^B .. A^(B i)
+    // (with their byte copies) are written; `avail` is the largest such i
+    // seen complete with a clean status word, so queries n <= B (avail + 1)
+    // are answered before the build ends.
+    std::vector<hipEvent_t> step_ev;
+    int avail = 0;
+    bool failing = false;  // the build failed; no new queries while earlier ones drain
     int64_t *trace_dev = nullptr;
     int32_t *status_dev = nullptr;
     int inflight = 0;
@@ -267,6 +275,7 @@ struct Request {
 };
 
 struct Slot {
+    hipStream_t stream = nullptr;  // the query stream, or the early stream (the last slot)
     bool busy = false;
     hipEvent_t done = nullptr;
     TRDesc *desc_host = nullptr;  // pinned
@@ -280,7 +289,8 @@ struct Slot {
 struct Server {
     mpr_server_options opt;
     int device = 0;
-    hipStream_t qstream = nullptr, bstream = nullptr;
+    // queries of ready ladders / builds / queries of ladders still building
+    hipStream_t qstream = nullptr, bstream = nullptr, estream = nullptr;
     Clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv_in, cv_out;
@@ -438,6 +448,17 @@ static mpr_status start_build(Server &S, Ladder &L)
         for (int i = 1; i <= G; i++, p += mat8) L.Ng8[i] = (uint8_t *)p;
     }
     hipStream_t s = S.bstream;
+    // Byte copy of one finished ladder matrix for the query pass (half the
+    // bytes per query); ladder buffers are 256-byte aligned.
+    auto pack = [&](const u16 *src, uint8_t *dst) {
+        if (!bytes8 || n == 0) return MPR_OK;
+        hipLaunchKernelGGL(pack8_kernel, dim3((unsigned)n), dim3(256), 0, s, src, ld, dst, L.ld8, n, ld % 8 == 0 ? 1 : 0,
+                           L.wide_dev);
+        return check_launch();
+    };
+    L.step_ev.assign(G + 1, nullptr);
+    for (int i = 1; i <= G; i++)
+        if (hipEventCreateWithFlags(&L.step_ev[i], hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
     mpr_status e = fill_i32_launch(L.status_dev, 1, 0, s);
     if (e == MPR_OK) e = fill_i32_launch(L.wide_dev, 1, 0, s);
     if (e == MPR_OK) e = transfer_launch(L.m, A, ld, s);
@@ -469,22 +490,18 @@ static mpr_status start_build(Server &S, Ladder &L)
             e = normalise_launch(n, n, L.Nb[j], ld, L.Rb[j - 1], nullptr, L.Rb[j], L.status_dev, nullptr, s);
     }
     for (int j = 1; j <= B && e == MPR_OK; j++) e = trace_launch(L.Nb[j], n, ld, L.Rb[j], L.trace_dev + (j - 1), s);
+    for (int j = 1; j <= B && e == MPR_OK; j++) e = pack(L.Nb[j], L.Nb8[j]);
+    // Then the giants in order, each announced by its event once written
+    // (with its byte copy): the queries that need no later giant go ahead.
+    if (G >= 1 && e == MPR_OK) e = pack(L.Ng[1], L.Ng8[1]);
+    if (G >= 1 && e == MPR_OK && hipEventRecord(L.step_ev[1], s) != hipSuccess) e = MPR_EHIP;
     if (G >= 2 && e == MPR_OK) e = fold_launch(L.Ng[1], ld, L.Rg[1], n, n, Bp, ld, scal, L.status_dev, s);
     for (int i = 2; i <= G && e == MPR_OK; i++) {
         e = gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, Bp, ld, L.Ng[i], ld, s);
         if (e == MPR_OK)
             e = normalise_launch(n, n, L.Ng[i], ld, L.Rg[i - 1], scal, L.Rg[i], L.status_dev, nullptr, s);
-    }
-    // byte copies for the query pass (half the bytes per query)
-    if (bytes8 && n > 0 && e == MPR_OK) {
-        const int vec8 = ld % 8 == 0;  // ladder buffers are 256-byte aligned
-        for (int k = 1; k <= B + G && e == MPR_OK; k++) {
-            const u16 *src = k <= B ? L.Nb[k] : L.Ng[k - B];
-            uint8_t *dst = k <= B ? L.Nb8[k] : L.Ng8[k - B];
-            hipLaunchKernelGGL(pack8_kernel, dim3((unsigned)n), dim3(256), 0, s, src, ld, dst, L.ld8, n, vec8,
-                               L.wide_dev);
-            e = check_launch();
-        }
+        if (e == MPR_OK) e = pack(L.Ng[i], L.Ng8[i]);
+        if (e == MPR_OK && hipEventRecord(L.step_ev[i], s) != hipSuccess) e = MPR_EHIP;
     }
     if (e != MPR_OK) return e;
     if (hipEventCreateWithFlags(&L.ready, hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
@@ -500,6 +517,8 @@ static void free_ladder(Server &S, Ladder &L)
 {
     if (L.pb && L.pb->th.joinable()) L.pb->th.join();  // a period-mode build still running
     if (L.ready) (void)hipEventDestroy(L.ready);
+    for (hipEvent_t ev : L.step_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (L.mem) (void)hipFree(L.mem);
     S.resident -= L.bytes;
     L = Ladder();
@@ -586,10 +605,80 @@ static bool admit(Server &S, int m)
             (void)hipEventDestroy(L.ready);
             L.ready = nullptr;
         }
+        for (hipEvent_t &ev : L.step_ev)
+            if (ev) {
+                (void)hipEventDestroy(ev);
+                ev = nullptr;
+            }
         L.state = Ladder::FAILED;
         L.fail_status = e;
     }
     return true;  // building, or failed (reported to the waiting requests)
+}
+
+// One grouped launch of `batch` on a free slot's stream.
+static void launch_batch(Server &S, Slot *slot, std::vector<Request> &batch)
+{
+    if (!slot || batch.empty()) return;
+    const int64_t B = S.opt.baby;
+    // Queries on byte copies that share a giant power (same m and i)
+    // go in groups of up to TR_GROUP, which read it once; the order
+    // of the batch follows the groups.
+    std::stable_sort(batch.begin(), batch.end(), [B](const Request &x, const Request &y) {
+        const int64_t ix = (x.n - 1) / B, iy = (y.n - 1) / B;
+        return x.m != y.m ? x.m < y.m : ix < iy;
+    });
+    int64_t blocks = 0, shared = 0;
+    int lead = 0;
+    for (size_t q = 0; q < batch.size(); q++) {
+        const Request &r = batch[q];
+        Ladder &L = S.ladders[r.m];
+        const int64_t i = (r.n - 1) / B, j = r.n - B * i;
+        const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
+        const TRDesc &head = slot->desc_host[lead];  // of the group the query may join
+        const bool join = q > 0 && L.narrow && head.narrow && head.X8 == L.Ng8[i] && head.gsize < TR_GROUP;
+        if (!join) lead = (int)q;
+        const int64_t first = join ? head.first_block : blocks;
+        slot->desc_host[q] = TRDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.Ng8[i], L.Nb8[j],
+                                    L.n,     L.ld,     L.ld8,    first,    vec,      L.narrow ? 1 : 0,
+                                    (int)q - lead, 1};
+        if (join) {
+            slot->desc_host[lead].gsize++;
+            shared++;
+        } else
+            blocks += trace_blocks(L.n);
+        L.inflight++;
+        L.last_use = S.now();
+    }
+    const int nq = (int)batch.size();
+    hipStream_t s = slot->stream;
+    bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TRDesc) * nq, hipMemcpyHostToDevice,
+                             s) == hipSuccess;
+    const int64_t pitch = slot_pitch(nq);
+    const int words = (int)(TR_SLOTS * pitch);
+    hipLaunchKernelGGL(fill_none_kernel, dim3((words + 255) / 256), dim3(256), 0, s, slot->out_dev, words);
+    hipLaunchKernelGGL(grouped_trace_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
+                       nq, pitch, slot->out_dev);
+    ok = ok && hipGetLastError() == hipSuccess;
+    ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * (size_t)words, hipMemcpyDeviceToHost, s) ==
+                   hipSuccess;
+    ok = ok && hipEventRecord(slot->done, s) == hipSuccess;
+    if (!ok) {
+        S.fatal = "launch failed";
+        for (auto &r : batch) {
+            S.ladders[r.m].inflight--;
+            complete(S, r, ROW_NONE, MPR_EHIP, S.now());
+        }
+        return;
+    }
+    slot->reqs = batch;
+    slot->busy = true;
+    slot->t_launch = S.now();
+    stats_update(S, [nq, shared](mpr_server_stats &t) {
+        t.batches++;
+        t.shared_reads += shared;
+        t.max_batch_seen = std::max<int64_t>(t.max_batch_seen, nq);
+    });
 }
 
 static void worker_main(Server *Sp)
@@ -666,27 +755,55 @@ static void worker_main(Server *Sp)
                 L.fail_status = st;
             }
         }
-        for (auto &kv : S.ladders) {
-            Ladder &L = kv.second;
-            if (L.state != Ladder::BUILDING || L.period || hipEventQuery(L.ready) != hipSuccess) continue;
+        // The status word, the byte-copy flag and (first time) the baby
+        // traces, read once the build's stream has passed an event.
+        auto read_build = [&](Ladder &L, bool traces) {
             int32_t st = 0, wide = 1;
-            L.baby_trace.assign(B + 1, ROW_NONE);
+            if (traces) L.baby_trace.assign(B + 1, ROW_NONE);
             if (hipMemcpy(&st, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
                 hipMemcpy(&wide, L.wide_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                (traces && hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) !=
+                               hipSuccess))
                 st = MPR_EHIP;
+            // The flag only rises: a launch that read byte copies did so
+            // while every copy it read was known to fit.
             L.narrow = !S.opt.wide_only && wide == 0;
-            if (st == 0 && L.narrow) stats_update(S, [](mpr_server_stats &t) { t.narrow_builds++; });
-            L.build_s = S.now() - L.build_s0;
-            L.last_use = S.now();
-            if (st == 0) {
-                L.state = Ladder::READY;
-            } else {  // the build is done with its memory: release it, keep the verdict
-                free_ladder(S, L);
-                L.m = kv.first;
-                L.state = Ladder::FAILED;
-                L.fail_status = st;
+            return st;
+        };
+        for (auto &kv : S.ladders) {
+            Ladder &L = kv.second;
+            if (L.state != Ladder::BUILDING || L.period) continue;
+            // Events complete in order: find the last one passed, then read
+            // the words once for all of them.
+            const int G = (int)L.step_ev.size() - 1;
+            int k = L.avail;
+            while (!L.failing && k < G && hipEventQuery(L.step_ev[k + 1]) == hipSuccess) k++;
+            if (k > L.avail) {
+                if (read_build(L, L.avail == 0) == 0)
+                    L.avail = k;
+                else
+                    L.failing = true;  // reported once the build's last event has passed
             }
+            if (hipEventQuery(L.ready) != hipSuccess) continue;
+            const int32_t st = L.failing ? MPR_EHIP : read_build(L, L.avail == 0);
+            if (st == 0) {
+                if (L.narrow) stats_update(S, [](mpr_server_stats &t) { t.narrow_builds++; });
+                L.build_s = S.now() - L.build_s0;
+                L.last_use = S.now();
+                L.avail = G;
+                L.state = Ladder::READY;
+                continue;
+            }
+            // The build is done with its memory: once no launch reads it any
+            // more, release it and keep the verdict.
+            L.failing = true;
+            if (L.inflight > 0) continue;
+            int32_t why = st;
+            if (hipMemcpy(&why, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess || why == 0) why = MPR_EHIP;
+            free_ladder(S, L);
+            L.m = kv.first;
+            L.state = Ladder::FAILED;
+            L.fail_status = why;
         }
         // 3. route new requests
         for (auto &r : fresh) {
@@ -719,15 +836,18 @@ static void worker_main(Server *Sp)
             else
                 k++;
         }
-        // 5. one grouped launch for everything that is ready
-        Slot *slot = nullptr;
+        // 5. one grouped launch for everything that is ready, and one on the
+        // early stream for queries of ladders still building: their passes
+        // share the device with the build's products, and behind them on
+        // one stream the warm queries would wait for those products too.
+        Slot *slot = nullptr, *eslot = nullptr;
         for (auto &sl : S.slots)
             if (!sl.busy) {
-                slot = &sl;
-                break;
+                Slot *&to = sl.stream == S.estream ? eslot : slot;
+                if (!to) to = &sl;
             }
-        std::vector<Request> batch;
-        int64_t batch_blocks = 0;  // grid of the grouped launch
+        std::vector<Request> batch, ebatch;
+        int64_t batch_blocks = 0, ebatch_blocks = 0;  // grids of the grouped launches
         for (auto &kv : S.waiting) {
             Ladder &L = S.ladders[kv.first];
             if (L.state == Ladder::FAILED) {
@@ -739,7 +859,10 @@ static void worker_main(Server *Sp)
                 L = Ladder();
                 continue;
             }
-            if (L.state != Ladder::READY) continue;
+            // A ready ladder answers every query; one still building, those
+            // whose giant is already written.
+            const bool early = L.state == Ladder::BUILDING && !L.period && !L.failing && L.avail >= 1;
+            if (L.state != Ladder::READY && !early) continue;
             auto &dq = kv.second;
             if (L.period) {  // the labelled fast mode: a table read per query
                 const int64_t cnt = (int64_t)dq.size();
@@ -748,82 +871,36 @@ static void worker_main(Server *Sp)
                 if (cnt) stats_update(S, [cnt](mpr_server_stats &t) { t.period_answers += cnt; });
                 continue;
             }
-            while (!dq.empty()) {
-                Request r = dq.front();
+            int64_t answered_early = 0;
+            for (auto it = dq.begin(); it != dq.end();) {
+                const Request r = *it;
                 const int64_t i = (r.n - 1) / B, j = r.n - B * i;
+                if (i > L.avail) {  // its giant is not written yet (only while building)
+                    ++it;
+                    continue;
+                }
                 if (i == 0) {  // read off the build's trace of A^j
-                    dq.pop_front();
+                    it = dq.erase(it);
                     L.last_use = S.now();
+                    answered_early += early;
                     complete(S, r, L.baby_trace[j], MPR_OK, S.now());
                     continue;
                 }
                 const int64_t qb = trace_blocks(L.n);
-                if (!slot || (int)batch.size() >= S.opt.max_batch || batch_blocks + qb > INT32_MAX) break;
-                dq.pop_front();
-                batch.push_back(r);
-                batch_blocks += qb;
+                Slot *to = early ? eslot : slot;
+                std::vector<Request> &tb = early ? ebatch : batch;
+                int64_t &tbb = early ? ebatch_blocks : batch_blocks;
+                if (!to || (int)tb.size() >= S.opt.max_batch || tbb + qb > INT32_MAX) break;
+                it = dq.erase(it);
+                answered_early += early;
+                tb.push_back(r);
+                tbb += qb;
             }
+            if (answered_early)
+                stats_update(S, [answered_early](mpr_server_stats &t) { t.early_answers += answered_early; });
         }
-        if (slot && !batch.empty()) {
-            // Queries on byte copies that share a giant power (same m and i)
-            // go in groups of up to TR_GROUP, which read it once; the order
-            // of the batch follows the groups.
-            std::stable_sort(batch.begin(), batch.end(), [B](const Request &x, const Request &y) {
-                const int64_t ix = (x.n - 1) / B, iy = (y.n - 1) / B;
-                return x.m != y.m ? x.m < y.m : ix < iy;
-            });
-            int64_t blocks = 0, shared = 0;
-            int lead = 0;
-            for (size_t q = 0; q < batch.size(); q++) {
-                const Request &r = batch[q];
-                Ladder &L = S.ladders[r.m];
-                const int64_t i = (r.n - 1) / B, j = r.n - B * i;
-                const int vec = aligned16(L.Ng[i]) && aligned16(L.Nb[j]) && L.ld % 8 == 0;
-                const TRDesc &head = slot->desc_host[lead];  // of the group the query may join
-                const bool join = q > 0 && L.narrow && head.narrow && head.X8 == L.Ng8[i] && head.gsize < TR_GROUP;
-                if (!join) lead = (int)q;
-                const int64_t first = join ? head.first_block : blocks;
-                slot->desc_host[q] = TRDesc{L.Ng[i], L.Rg[i], L.Nb[j], L.Rb[j], L.Ng8[i], L.Nb8[j],
-                                            L.n,     L.ld,     L.ld8,    first,    vec,      L.narrow ? 1 : 0,
-                                            (int)q - lead, 1};
-                if (join) {
-                    slot->desc_host[lead].gsize++;
-                    shared++;
-                } else
-                    blocks += trace_blocks(L.n);
-                L.inflight++;
-                L.last_use = S.now();
-            }
-            const int nq = (int)batch.size();
-            hipStream_t s = S.qstream;
-            bool ok = hipMemcpyAsync(slot->desc_dev, slot->desc_host, sizeof(TRDesc) * nq, hipMemcpyHostToDevice,
-                                     s) == hipSuccess;
-            const int64_t pitch = slot_pitch(nq);
-            const int words = (int)(TR_SLOTS * pitch);
-            hipLaunchKernelGGL(fill_none_kernel, dim3((words + 255) / 256), dim3(256), 0, s, slot->out_dev, words);
-            hipLaunchKernelGGL(grouped_trace_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slot->desc_dev,
-                               nq, pitch, slot->out_dev);
-            ok = ok && hipGetLastError() == hipSuccess;
-            ok = ok && hipMemcpyAsync(slot->out_host, slot->out_dev, 8 * (size_t)words, hipMemcpyDeviceToHost, s) ==
-                           hipSuccess;
-            ok = ok && hipEventRecord(slot->done, s) == hipSuccess;
-            if (!ok) {
-                S.fatal = "launch failed";
-                for (auto &r : batch) {
-                    S.ladders[r.m].inflight--;
-                    complete(S, r, ROW_NONE, MPR_EHIP, S.now());
-                }
-                continue;
-            }
-            slot->reqs = batch;
-            slot->busy = true;
-            slot->t_launch = S.now();
-            stats_update(S, [nq, shared](mpr_server_stats &t) {
-                t.batches++;
-                t.shared_reads += shared;
-                t.max_batch_seen = std::max<int64_t>(t.max_batch_seen, nq);
-            });
-        }
+        launch_batch(S, slot, batch);
+        launch_batch(S, eslot, ebatch);
         stats_update(S, [&S](mpr_server_stats &t) { t.resident_bytes = (int64_t)S.resident; });
     }
 }
@@ -846,9 +923,12 @@ extern "C" mpr_status mpr_server_create(const mpr_server_options *opt, void **se
     memset(&S->stats, 0, sizeof(S->stats));
     S->t0 = Clock::now();
     bool ok = hipStreamCreateWithFlags(&S->qstream, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&S->bstream, hipStreamNonBlocking) == hipSuccess;
-    S->slots.resize(opt->slots);
-    for (auto &sl : S->slots) {
+              hipStreamCreateWithFlags(&S->bstream, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&S->estream, hipStreamNonBlocking) == hipSuccess;
+    S->slots.resize(opt->slots + 1);  // the last one launches on the early stream
+    for (size_t k = 0; k < S->slots.size(); k++) {
+        Slot &sl = S->slots[k];
+        sl.stream = k + 1 < S->slots.size() ? S->qstream : S->estream;
         ok = ok && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&sl.desc_host, sizeof(TRDesc) * opt->max_batch) == hipSuccess;
         const size_t words = (size_t)TR_SLOTS * (size_t)slot_pitch(opt->max_batch);
@@ -939,6 +1019,7 @@ extern "C" mpr_status mpr_server_destroy(void *server)
     if (S->worker.joinable()) S->worker.join();
     if (S->qstream) (void)hipStreamSynchronize(S->qstream);
     if (S->bstream) (void)hipStreamSynchronize(S->bstream);
+    if (S->estream) (void)hipStreamSynchronize(S->estream);
     for (auto &kv : S->ladders)
         if (kv.second.mem) free_ladder(*S, kv.second);
     for (auto &sl : S->slots) {
@@ -950,6 +1031,7 @@ extern "C" mpr_status mpr_server_destroy(void *server)
     }
     if (S->qstream) (void)hipStreamDestroy(S->qstream);
     if (S->bstream) (void)hipStreamDestroy(S->bstream);
+    if (S->estream) (void)hipStreamDestroy(S->estream);
     delete S;
     return MPR_OK;
 }

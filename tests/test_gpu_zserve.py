@@ -142,10 +142,11 @@ def test_server_large_ladders_mixed_batches(serve, wide_only):
 def test_server_shared_giant_groups(serve):
     """Queries of one launch that share a giant power A^(32 i) are answered in
     groups of up to 8 that read it once.  A burst submitted while the ladders
-    of m = 7 and m = 8 (N = 2507, 7411) are still being built, so each
-    ladder's queries are ready together and go in one launch: 20 queries on
-    A^160 of m = 8 (groups of 8, 8, 4), 10 on A^288 of m = 7 (8, 2) and four
-    alone; every answer equal to its answer alone and to the stored tables."""
+    of m = 7 and m = 8 (N = 2507, 7411) are still being built, so the queries
+    on one giant become answerable together (when the build has written it)
+    and go in one launch: 20 queries on A^160 of m = 8 (groups of 8, 8, 4),
+    10 on A^288 of m = 7 (8, 2) and four alone; every answer equal to its
+    answer alone and to the stored tables."""
     qs = [(8, 160 + j) for j in range(1, 21)] + [(7, 288 + j) for j in range(3, 31, 3)]
     qs += [(8, 999), (7, 40), (8, 100), (7, 641)]
     rng = np.random.default_rng(23)
@@ -157,6 +158,9 @@ def test_server_shared_giant_groups(serve):
         while len(got) < len(qs) and time.monotonic() < t_end:
             for r in S.poll(50):
                 got[r["tag"]] = r
+        # the last answers may come from a ladder whose build is still ending
+        while S.stats()["narrow_builds"] < 2 and time.monotonic() < t_end:
+            time.sleep(0.01)
         st = S.stats()
         alone = {q: S.query(*q)["gamma"] for q in set(qs)}
         st1 = S.stats()
@@ -241,6 +245,32 @@ def test_warm_queries_overlap_a_cold_build(serve):
         r = got[k]
         assert r["status"] == 0 and r["cold"] == 0 and r["gamma"] == golden_gamma(m, n), (m, n)
         assert r["t_done"] < big["t_done"] and r["t_submit"] > big["t_submit"]
+
+
+def test_cold_ladder_answers_progressively(serve):
+    """A ladder still being built answers the queries whose giant power is
+    already written (the build announces each giant by an event): on a fresh
+    engine, m = 8 queries n = 3 (a baby trace), 40 (giant 1), 70 (giant 2),
+    500 (giant 15) and 999 (giant 31) submitted at once are answered in giant
+    order, the first ones while the later giants are still being computed,
+    each equal to the stored gamma_R table."""
+    ns = [999, 500, 70, 40, 3]
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=4, hbm_budget_bytes=200 << 30) as S:
+        for k, n in enumerate(ns):
+            S.submit(8, n, k)
+        got, t_end = {}, time.monotonic() + 120
+        while len(got) < len(ns) and time.monotonic() < t_end:
+            for r in S.poll(20):
+                got[r["tag"]] = r
+        st = S.stats()
+        assert S.query(8, 999)["gamma"] == golden_gamma(8, 999)  # and from the finished ladder
+    t = {n: got[k]["t_done"] for k, n in enumerate(ns)}
+    for k, n in enumerate(ns):
+        r = got[k]
+        assert r["status"] == 0 and r["cold"] == 1 and r["gamma"] == golden_gamma(8, n), n
+    assert t[3] <= t[40] < t[500] < t[999]
+    assert t[70] < t[999]
+    assert st["early_answers"] >= 3 and st["builds"] == 1
 
 
 def test_build_refused_without_free_memory_then_retried(serve):
