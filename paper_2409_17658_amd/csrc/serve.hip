@@ -245,6 +245,11 @@ struct Ladder {
     std::vector<uint8_t *> Nb8, Ng8;  // byte copies (row stride ld8), when the server keeps them
     int64_t ld8 = 0;
     int32_t *wide_dev = nullptr;      // set by the pack pass when an entry does not fit a byte
+    // Pinned host copy of the build's words (baby traces, status word,
+    // byte-copy flag), refreshed by the build stream before each of its
+    // events, so the worker reads them without a HIP call of its own (a
+    // blocking copy could wait behind the build on a shared hardware queue).
+    volatile int64_t *info = nullptr;
     bool narrow = false;              // queries read the byte copies
     std::vector<int64_t> baby_trace;  // host, index j = 1..B
     hipEvent_t ready = nullptr;
@@ -256,6 +261,13 @@ struct Ladder {
     std::vector<hipEvent_t> step_ev;
     int avail = 0;
     bool failing = false;  // the build failed; no new queries while earlier ones drain
+    // Giant products are handed to the build stream a few at a time (the
+    // worker tops them up as they finish), so whatever shares the stream's
+    // hardware queue, and the builds of other m, wait for at most those.
+    int next_giant = 0;      // next giant to enqueue
+    bool submitted = false;  // every step enqueued and `ready` recorded
+    u16 *Bp = nullptr;       // the folded A^B, right operand of every giant product
+    int64_t *scal = nullptr; // the build's scalar words on the device
     int64_t *trace_dev = nullptr;
     int32_t *status_dev = nullptr;
     int inflight = 0;
@@ -304,6 +316,7 @@ struct Server {
     std::deque<int> admission;                   // m values waiting for memory
     std::vector<Slot> slots;
     size_t resident = 0;
+    int64_t *info_host = nullptr;  // pinned, info_words(baby) words per m = 0..11
     mpr_server_stats stats;
     std::string fatal;
 
@@ -334,6 +347,19 @@ static size_t ladder_bytes(int m, int B, int G, bool bytes8, int64_t *n_out, int
 }
 
 static int giant_count(const mpr_server_options &o) { return (int)((o.max_n - 1) / o.baby); }
+
+// A ladder's pinned word copy: words 1 .. B + 3 of its scalar block, i.e.
+// the B baby traces, one unused word, the status word and the byte-copy
+// flag (each int32 in the low half of its word).
+static inline int info_words(int B) { return B + 3; }
+static inline int32_t info_status(volatile const int64_t *info, int B)
+{
+    return ((volatile const int32_t *)(info + B + 1))[0];
+}
+static inline int32_t info_wide(volatile const int64_t *info, int B)
+{
+    return ((volatile const int32_t *)(info + B + 2))[0];
+}
 
 // Ring powers of a period-mode search: confirms periods up to 7.
 constexpr int kPeriodSlots = 8;
@@ -403,7 +429,72 @@ static mpr_status start_period_build(Server &S, Ladder &L)
     return MPR_OK;
 }
 
-// Enqueues the whole ladder build on the build stream.
+// Giant products a build keeps enqueued beyond the last one finished.
+constexpr int kGiantsAhead = 2;
+
+// The build's words into the pinned copy (L.info), ahead of an event.
+static mpr_status publish_build(Server &S, Ladder &L)
+{
+    return hipMemcpyAsync((void *)L.info, L.scal + 1, 8 * (size_t)info_words(S.opt.baby), hipMemcpyDeviceToHost,
+                          S.bstream) == hipSuccess
+               ? MPR_OK
+               : MPR_EHIP;
+}
+
+// Byte copy of one finished ladder matrix for the query pass (half the
+// bytes per query); ladder buffers are 256-byte aligned.
+static mpr_status pack_build(Server &S, Ladder &L, const u16 *src, uint8_t *dst)
+{
+    if (S.opt.wide_only || L.n == 0) return MPR_OK;
+    hipLaunchKernelGGL(pack8_kernel, dim3((unsigned)L.n), dim3(256), 0, S.bstream, src, L.ld, dst, L.ld8, L.n,
+                       L.ld % 8 == 0 ? 1 : 0, L.wide_dev);
+    return check_launch();
+}
+
+// The build's last words and its `ready` event, after everything enqueued.
+static mpr_status finish_build(Server &S, Ladder &L)
+{
+    mpr_status e = publish_build(S, L);
+    if (hipEventRecord(L.ready, S.bstream) != hipSuccess) {
+        // Unrecorded, the event reads as complete: wait here for the work
+        // already enqueued instead.
+        (void)hipStreamSynchronize(S.bstream);
+        e = MPR_EHIP;
+    }
+    L.submitted = true;
+    return e;
+}
+
+// Enqueues giants L.next_giant .. upto (each with its byte copy, the words
+// and its event), then finishes the build once the last one is enqueued.
+// A failure marks the build failing and finishes it.
+static mpr_status enqueue_giants(Server &S, Ladder &L, int upto)
+{
+    const int G = (int)L.step_ev.size() - 1;
+    const int64_t n = L.n, ld = L.ld;
+    hipStream_t s = S.bstream;
+    mpr_status e = MPR_OK;
+    for (; !L.failing && L.next_giant <= std::min(upto, G) && e == MPR_OK; L.next_giant++) {
+        const int i = L.next_giant;
+        e = gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, L.Bp, ld, L.Ng[i], ld, s);
+        if (e == MPR_OK)
+            e = normalise_launch(n, n, L.Ng[i], ld, L.Rg[i - 1], L.scal, L.Rg[i], L.status_dev, nullptr, s);
+        if (e == MPR_OK) e = pack_build(S, L, L.Ng[i], L.Ng8[i]);
+        if (e == MPR_OK) e = publish_build(S, L);
+        if (e == MPR_OK && hipEventRecord(L.step_ev[i], s) != hipSuccess) e = MPR_EHIP;
+    }
+    if (e != MPR_OK) L.failing = true;
+    if (!L.submitted && (L.failing || L.next_giant > G)) {
+        const mpr_status f = finish_build(S, L);
+        if (e == MPR_OK) e = f;
+        if (f != MPR_OK) L.failing = true;
+    }
+    return e;
+}
+
+// Enqueues a ladder build on the build stream: A, the chain to A^B, the
+// babies and their traces at once, then the first giant products (the
+// worker enqueues the rest as earlier ones finish).
 static mpr_status start_build(Server &S, Ladder &L)
 {
     const int B = S.opt.baby, G = giant_count(S.opt);
@@ -439,6 +530,7 @@ static mpr_status start_build(Server &S, Ladder &L)
     L.trace_dev = scal + 1;
     L.status_dev = (int32_t *)(scal + 2 + B);
     L.wide_dev = (int32_t *)(scal + 3 + B);
+    L.info = S.info_host + (size_t)L.m * info_words(B);  // words 1 .. B + 3 of scal
     L.ld8 = round_up(n, 16);
     const size_t mat8 = (size_t)round_up(n * L.ld8, 256);
     L.Nb8.assign(B + 1, nullptr);
@@ -448,17 +540,12 @@ static mpr_status start_build(Server &S, Ladder &L)
         for (int i = 1; i <= G; i++, p += mat8) L.Ng8[i] = (uint8_t *)p;
     }
     hipStream_t s = S.bstream;
-    // Byte copy of one finished ladder matrix for the query pass (half the
-    // bytes per query); ladder buffers are 256-byte aligned.
-    auto pack = [&](const u16 *src, uint8_t *dst) {
-        if (!bytes8 || n == 0) return MPR_OK;
-        hipLaunchKernelGGL(pack8_kernel, dim3((unsigned)n), dim3(256), 0, s, src, ld, dst, L.ld8, n, ld % 8 == 0 ? 1 : 0,
-                           L.wide_dev);
-        return check_launch();
-    };
+    L.scal = scal;
+    auto pack = [&](const u16 *src, uint8_t *dst) { return pack_build(S, L, src, dst); };
     L.step_ev.assign(G + 1, nullptr);
     for (int i = 1; i <= G; i++)
         if (hipEventCreateWithFlags(&L.step_ev[i], hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
+    if (hipEventCreateWithFlags(&L.ready, hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
     mpr_status e = fill_i32_launch(L.status_dev, 1, 0, s);
     if (e == MPR_OK) e = fill_i32_launch(L.wide_dev, 1, 0, s);
     if (e == MPR_OK) e = transfer_launch(L.m, A, ld, s);
@@ -494,18 +581,13 @@ static mpr_status start_build(Server &S, Ladder &L)
     // Then the giants in order, each announced by its event once written
     // (with its byte copy): the queries that need no later giant go ahead.
     if (G >= 1 && e == MPR_OK) e = pack(L.Ng[1], L.Ng8[1]);
+    if (G >= 1 && e == MPR_OK) e = publish_build(S, L);
     if (G >= 1 && e == MPR_OK && hipEventRecord(L.step_ev[1], s) != hipSuccess) e = MPR_EHIP;
     if (G >= 2 && e == MPR_OK) e = fold_launch(L.Ng[1], ld, L.Rg[1], n, n, Bp, ld, scal, L.status_dev, s);
-    for (int i = 2; i <= G && e == MPR_OK; i++) {
-        e = gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, Bp, ld, L.Ng[i], ld, s);
-        if (e == MPR_OK)
-            e = normalise_launch(n, n, L.Ng[i], ld, L.Rg[i - 1], scal, L.Rg[i], L.status_dev, nullptr, s);
-        if (e == MPR_OK) e = pack(L.Ng[i], L.Ng8[i]);
-        if (e == MPR_OK && hipEventRecord(L.step_ev[i], s) != hipSuccess) e = MPR_EHIP;
-    }
     if (e != MPR_OK) return e;
-    if (hipEventCreateWithFlags(&L.ready, hipEventDisableTiming) != hipSuccess) return MPR_EHIP;
-    if (hipEventRecord(L.ready, s) != hipSuccess) return MPR_EHIP;
+    L.Bp = Bp;
+    L.next_giant = 2;
+    (void)enqueue_giants(S, L, 1 + kGiantsAhead);  // a failure is reported by the worker
     L.state = Ladder::BUILDING;
     L.build_s0 = S.now();
     S.resident += L.bytes;
@@ -756,15 +838,14 @@ static void worker_main(Server *Sp)
             }
         }
         // The status word, the byte-copy flag and (first time) the baby
-        // traces, read once the build's stream has passed an event.
+        // traces, from the pinned copy the build wrote before the event
+        // just seen complete.
         auto read_build = [&](Ladder &L, bool traces) {
-            int32_t st = 0, wide = 1;
-            if (traces) L.baby_trace.assign(B + 1, ROW_NONE);
-            if (hipMemcpy(&st, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(&wide, L.wide_dev, 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                (traces && hipMemcpy(L.baby_trace.data() + 1, L.trace_dev, (size_t)B * 8, hipMemcpyDeviceToHost) !=
-                               hipSuccess))
-                st = MPR_EHIP;
+            const int32_t st = info_status(L.info, B), wide = info_wide(L.info, B);
+            if (traces) {
+                L.baby_trace.assign(B + 1, ROW_NONE);
+                for (int j = 1; j <= B; j++) L.baby_trace[j] = L.info[j - 1];
+            }
             // The flag only rises: a launch that read byte copies did so
             // while every copy it read was known to fit.
             L.narrow = !S.opt.wide_only && wide == 0;
@@ -773,18 +854,21 @@ static void worker_main(Server *Sp)
         for (auto &kv : S.ladders) {
             Ladder &L = kv.second;
             if (L.state != Ladder::BUILDING || L.period) continue;
-            // Events complete in order: find the last one passed, then read
-            // the words once for all of them.
+            // Events complete in order: find the last one passed (among the
+            // recorded ones: an event never recorded reads as complete), then
+            // read the words once for all of them.
             const int G = (int)L.step_ev.size() - 1;
+            const int recorded = std::min(G, L.next_giant - 1);
             int k = L.avail;
-            while (!L.failing && k < G && hipEventQuery(L.step_ev[k + 1]) == hipSuccess) k++;
+            while (!L.failing && k < recorded && hipEventQuery(L.step_ev[k + 1]) == hipSuccess) k++;
             if (k > L.avail) {
                 if (read_build(L, L.avail == 0) == 0)
                     L.avail = k;
                 else
                     L.failing = true;  // reported once the build's last event has passed
             }
-            if (hipEventQuery(L.ready) != hipSuccess) continue;
+            if (!L.submitted) (void)enqueue_giants(S, L, std::max(L.avail, 1) + kGiantsAhead);
+            if (!L.submitted || hipEventQuery(L.ready) != hipSuccess) continue;
             const int32_t st = L.failing ? MPR_EHIP : read_build(L, L.avail == 0);
             if (st == 0) {
                 if (L.narrow) stats_update(S, [](mpr_server_stats &t) { t.narrow_builds++; });
@@ -798,8 +882,8 @@ static void worker_main(Server *Sp)
             // more, release it and keep the verdict.
             L.failing = true;
             if (L.inflight > 0) continue;
-            int32_t why = st;
-            if (hipMemcpy(&why, L.status_dev, 4, hipMemcpyDeviceToHost) != hipSuccess || why == 0) why = MPR_EHIP;
+            int32_t why = info_status(L.info, B);
+            if (why == 0) why = MPR_EHIP;
             free_ladder(S, L);
             L.m = kv.first;
             L.state = Ladder::FAILED;
@@ -925,6 +1009,7 @@ extern "C" mpr_status mpr_server_create(const mpr_server_options *opt, void **se
     bool ok = hipStreamCreateWithFlags(&S->qstream, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&S->bstream, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&S->estream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&S->info_host, 8 * (size_t)12 * (size_t)info_words(opt->baby)) == hipSuccess;
     S->slots.resize(opt->slots + 1);  // the last one launches on the early stream
     for (size_t k = 0; k < S->slots.size(); k++) {
         Slot &sl = S->slots[k];
@@ -1032,6 +1117,7 @@ extern "C" mpr_status mpr_server_destroy(void *server)
     if (S->qstream) (void)hipStreamDestroy(S->qstream);
     if (S->bstream) (void)hipStreamDestroy(S->bstream);
     if (S->estream) (void)hipStreamDestroy(S->estream);
+    if (S->info_host) (void)hipHostFree(S->info_host);
     delete S;
     return MPR_OK;
 }
