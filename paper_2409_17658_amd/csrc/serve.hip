@@ -429,8 +429,19 @@ static mpr_status start_period_build(Server &S, Ladder &L)
     return MPR_OK;
 }
 
-// Giant products a build keeps enqueued beyond the last one finished.
-constexpr int kGiantsAhead = 2;
+// Giant products are scheduled across the ladders being built, shortest
+// first: a small ladder (N < kBigLadder, products of microseconds) keeps up
+// to kSmallAhead of its products enqueued; of the large ones (milliseconds
+// to a third of a second each) at most one product is enqueued at a time,
+// taken from the ladder with the least N.  So a launch behind the build on
+// a shared hardware queue waits for at most one large product, and a
+// smaller ladder is never stuck behind a larger one's products (the
+// worker's tick between two large products costs well under 1 %).
+constexpr int64_t kBigLadder = 4096;
+constexpr int kSmallAhead = 8;
+
+// Giant products of L enqueued and not yet finished.
+static inline int giants_in_flight(const Ladder &L) { return (L.next_giant - 1) - std::max(L.avail, 1); }
 
 // The build's words into the pinned copy (L.info), ahead of an event.
 static mpr_status publish_build(Server &S, Ladder &L)
@@ -587,7 +598,7 @@ static mpr_status start_build(Server &S, Ladder &L)
     if (e != MPR_OK) return e;
     L.Bp = Bp;
     L.next_giant = 2;
-    (void)enqueue_giants(S, L, 1 + kGiantsAhead);  // a failure is reported by the worker
+    (void)enqueue_giants(S, L, 1);  // no giant yet (the worker schedules them); finishes when G <= 1
     L.state = Ladder::BUILDING;
     L.build_s0 = S.now();
     S.resident += L.bytes;
@@ -867,7 +878,33 @@ static void worker_main(Server *Sp)
                 else
                     L.failing = true;  // reported once the build's last event has passed
             }
-            if (!L.submitted) (void)enqueue_giants(S, L, std::max(L.avail, 1) + kGiantsAhead);
+        }
+        {  // schedule the next giant products (shortest ladder first)
+            std::vector<Ladder *> order;
+            int big = 0;
+            for (auto &kv : S.ladders) {
+                Ladder &L = kv.second;
+                if (L.state != Ladder::BUILDING || L.period || L.submitted) continue;
+                order.push_back(&L);
+                if (L.n >= kBigLadder) big += giants_in_flight(L);
+            }
+            std::sort(order.begin(), order.end(), [](const Ladder *x, const Ladder *y) { return x->n < y->n; });
+            for (Ladder *L : order) {
+                const int from = std::max(L->avail, 1);
+                if (L->failing)
+                    (void)enqueue_giants(S, *L, 0);  // finishes the build
+                else if (L->n < kBigLadder)
+                    (void)enqueue_giants(S, *L, from + kSmallAhead);
+                else if (big == 0) {
+                    (void)enqueue_giants(S, *L, from + 1);
+                    big += giants_in_flight(*L);
+                }
+            }
+        }
+        for (auto &kv : S.ladders) {
+            Ladder &L = kv.second;
+            if (L.state != Ladder::BUILDING || L.period) continue;
+            const int G = (int)L.step_ev.size() - 1;
             if (!L.submitted || hipEventQuery(L.ready) != hipSuccess) continue;
             const int32_t st = L.failing ? MPR_EHIP : read_build(L, L.avail == 0);
             if (st == 0) {
