@@ -23,10 +23,9 @@ using Cfg6 = TileCfg<256, 128, 32, 8, 8>;    // 512 threads, 8x8 per lane
 // Renumber so that each XCD receives a contiguous run of tiles, and walk the
 // tiles in groups of G tile-rows so that the blocks resident on one XCD share
 // A row panels and B column panels in that XCD's L2.
-__device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
+__device__ __forceinline__ bool tile_of(int b, int nb, int tiles_m, int tiles_n, int &tm, int &tn)
 {
-    const int nb = (int)gridDim.x;  // a multiple of 8
-    const int b = (int)blockIdx.x;
+    // nb: a multiple of 8
     const int t = (b & 7) * (nb >> 3) + (b >> 3);
     if (t >= tiles_m * tiles_n) return false;
     constexpr int G = 8;
@@ -37,6 +36,10 @@ __device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm,
     tm = first + w % gs;
     tn = w / gs;
     return true;
+}
+__device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
+{
+    return tile_of((int)blockIdx.x, (int)gridDim.x, tiles_m, tiles_n, tm, tn);
 }
 
 // Waves per SIMD the register allocation must allow: 4 (<= 128 VGPRs) for
@@ -61,6 +64,29 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(GemmWaves
     tile_store<T>(C, ldc, M, N, m0, n0, vec != 0, acc);
 }
 
+// The same product from a grid smaller than its block count: block b takes
+// the tiles of virtual blocks b, b + grid, ... of a virtual grid of
+// `vblocks` (both multiples of 8, so a virtual block runs on the XCD it
+// would have run on in the one-block-per-tile launch).  A grid below the
+// device's resident capacity leaves workgroup slots free for other work for
+// as long as the product runs.
+template <class T, bool H>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value))) void gemm_grid_kernel(
+    const u16 *__restrict__ A, int64_t lda, const u16 *__restrict__ B, int64_t ldb, u16 *__restrict__ C, int64_t ldc,
+    int64_t M, int64_t N, int64_t K, int tiles_m, int tiles_n, int vec, int vblocks)
+{
+    __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
+    for (int vb = (int)blockIdx.x; vb < vblocks; vb += (int)gridDim.x) {  // block-uniform
+        int tm, tn;
+        if (!tile_of(vb, vblocks, tiles_m, tiles_n, tm, tn)) continue;
+        const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
+        TileAcc<T> acc;
+        tile_mainloop<T, H>(A, lda, B, ldb, M, N, K, m0, n0, vec != 0, lds, acc);
+        tile_store<T>(C, ldc, M, N, m0, n0, vec != 0, acc);
+        __syncthreads();  // the next tile refills lds
+    }
+}
+
 // An empty inner dimension: every entry of C is infinite.
 __global__ void fill_inf_kernel(u16 *C, int64_t ldc, int64_t M, int64_t N)
 {
@@ -83,17 +109,53 @@ static mpr_status launch_cfg(int64_t M, int64_t N, int64_t K, const u16 *A, int6
     return check_launch();
 }
 
+// The grid form with at most max_blocks blocks (a multiple of 8); the
+// one-block-per-tile launch when the tiles fit in it.
+template <class T, bool H>
+static mpr_status launch_cfg_grid(int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
+                                  int64_t ldb, u16 *C, int64_t ldc, int max_blocks, hipStream_t s)
+{
+    const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+    const int64_t tiles = tiles_m * tiles_n;
+    if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
+    const int64_t blocks = round_up(tiles, 8);
+    if (max_blocks < 8 || blocks <= max_blocks) return launch_cfg<T, H>(M, N, K, A, lda, B, ldb, C, ldc, s);
+    const bool vec = aligned16(A) && aligned16(B) && aligned16(C) && lda % 8 == 0 && ldb % 8 == 0 && ldc % 8 == 0;
+    hipLaunchKernelGGL((gemm_grid_kernel<T, H>), dim3((unsigned)(max_blocks & ~7)), dim3(T::NT), 0, s, A, lda, B, ldb,
+                       C, ldc, M, N, K, (int)tiles_m, (int)tiles_n, vec ? 1 : 0, (int)blocks);
+    return check_launch();
+}
+
+// Workgroups of the grid form resident per CU.
+template <class T, bool H>
+static int grid_occupancy()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)gemm_grid_kernel<T, H>, T::NT, 0) !=
+            hipSuccess ||
+        b < 1) {
+        (void)hipGetLastError();
+        b = 1;
+    }
+    return b;
+}
+
 struct CfgInfo {
     int bm, bn, bk, tm, tn, nt, arith;
     mpr_status (*launch)(int64_t, int64_t, int64_t, const u16 *, int64_t, const u16 *, int64_t, u16 *, int64_t,
                          hipStream_t);
+    mpr_status (*launch_grid)(int64_t, int64_t, int64_t, const u16 *, int64_t, const u16 *, int64_t, u16 *,
+                              int64_t, int, hipStream_t);
+    int (*occupancy)();
 };
 
 // Configurations 0..5 compute in uint16 (MPR_ARITH_U16); 6..11 are the
 // same tiles in the f16 form with the uint16 recomputation of inexact blocks
 // (MPR_ARITH_F16), which gives the same product bit for bit.  12 is a
 // 512-thread tile in uint16, 13 the same in the f16 form.
-#define MPR_CFG(T, H) {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, H ? MPR_ARITH_F16 : MPR_ARITH_U16, launch_cfg<T, H>}
+#define MPR_CFG(T, H)                                                                                 \
+    {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, H ? MPR_ARITH_F16 : MPR_ARITH_U16, launch_cfg<T, H>,       \
+     launch_cfg_grid<T, H>, grid_occupancy<T, H>}
 static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0, false), MPR_CFG(Cfg1, false), MPR_CFG(Cfg2, false),
                                 MPR_CFG(Cfg3, false), MPR_CFG(Cfg4, false), MPR_CFG(Cfg5, false),
                                 MPR_CFG(Cfg0, true),  MPR_CFG(Cfg1, true),  MPR_CFG(Cfg2, true),
@@ -140,6 +202,20 @@ mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, i
     if (cfg < 0) cfg = pick_config(M, N, K);
     if (cfg >= kNumCfgs) return MPR_EINVAL;
     return kCfgs[cfg].launch(M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
+mpr_status gemm_launch_spare(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
+                             int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
+{
+    if (M == 0 || N == 0 || K == 0) return gemm_launch(cfg, M, N, K, A, lda, B, ldb, C, ldc, s);
+    if (cfg < 0) cfg = pick_config(M, N, K);
+    if (cfg >= kNumCfgs) return MPR_EINVAL;
+    static std::atomic<int> occ[kNumCfgs];  // 0: not yet asked
+    int o = occ[cfg].load();
+    if (o == 0) occ[cfg] = o = kCfgs[cfg].occupancy();
+    const int64_t cap = (int64_t)o * device_cu_count();
+    const int max_blocks = (int)std::min<int64_t>(INT32_MAX, cap * 7 / 8) & ~7;
+    return kCfgs[cfg].launch_grid(M, N, K, A, lda, B, ldb, C, ldc, max_blocks, s);
 }
 
 }  // namespace mpr

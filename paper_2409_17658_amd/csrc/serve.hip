@@ -487,7 +487,10 @@ static mpr_status enqueue_giants(Server &S, Ladder &L, int upto)
     mpr_status e = MPR_OK;
     for (; !L.failing && L.next_giant <= std::min(upto, G) && e == MPR_OK; L.next_giant++) {
         const int i = L.next_giant;
-        e = gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, L.Bp, ld, L.Ng[i], ld, s);
+        // large products leave an eighth of the device's workgroup slots to
+        // the queries that run beside the build
+        e = n >= kBigLadder ? gemm_launch_spare(-1, n, n, n, L.Ng[i - 1], ld, L.Bp, ld, L.Ng[i], ld, s)
+                            : gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, L.Bp, ld, L.Ng[i], ld, s);
         if (e == MPR_OK)
             e = normalise_launch(n, n, L.Ng[i], ld, L.Rg[i - 1], L.scal, L.Rg[i], L.status_dev, nullptr, s);
         if (e == MPR_OK) e = pack_build(S, L, L.Ng[i], L.Ng8[i]);
