@@ -152,6 +152,21 @@ mpr_status mpr_minplus_gemm_cfg(int cfg, int64_t M, int64_t N, int64_t K,
                                 uint16_t *C, int64_t ldc,
                                 int32_t *d_status, mpr_stream stream);
 
+/* The same product (same configurations, same bits) from a grid of at most
+ * 7/8 of the device's resident workgroups of the configuration, each looping
+ * over tiles, so that work on other streams finds free workgroup slots for
+ * as long as the product runs (without it a long product holds every slot
+ * until its blocks retire).  For callers that run long products beside
+ * latency-sensitive work: the query server builds its large ladders with
+ * it.  Products with fewer tiles than the grid take the plain launch.
+ * cfg = -1 picks from the tile table.  Arguments and errors as
+ * mpr_minplus_gemm. */
+mpr_status mpr_minplus_gemm_spare(int cfg, int64_t M, int64_t N, int64_t K,
+                                  const uint16_t *A, int64_t lda,
+                                  const uint16_t *B, int64_t ldb,
+                                  uint16_t *C, int64_t ldc,
+                                  int32_t *d_status, mpr_stream stream);
+
 /* Row-min normalisation in place: for each row i of the M x N matrix C,
  * r_i = least finite entry, C[i][:] -= r_i (MPR_INF stays), and
  * R_out[i] = R_in[i] + r_i (R_in may be NULL, read as 0; R_in may equal

@@ -85,6 +85,7 @@ _SIGS = {
     "mpr_build_transfer": (_I, [_I, _P, _I64, _P]),
     "mpr_build_border_transfer": (_I, [_I, _P, _I64, _P, _P]),
     "mpr_minplus_gemm": (_I, [_I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
+    "mpr_minplus_gemm_spare": (_I, [_I, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
     "mpr_minplus_gemm_cfg": (_I, [_I, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _P]),
     "mpr_normalise": (_I, [_I64, _I64, _P, _I64, _P, _P, _P, _P]),
     "mpr_gemm_norm_workspace_size": (_I, [_I64, _I64, _P]),
@@ -280,7 +281,9 @@ def build_border_transfer(m: int, out=None, stream=None):
     return A, sh.value
 
 
-def minplus_gemm(A, B, C=None, check=True, cfg=-1, stream=None, d_status=None):
+def minplus_gemm(A, B, C=None, check=True, cfg=-1, stream=None, d_status=None, spare=False):
+    """C = A (x) B.  spare=True: the grid form that leaves an eighth of the
+    device's workgroup slots free while it runs (same bits)."""
     M, K = A.shape
     K2, N = B.shape
     if K != K2:
@@ -288,8 +291,9 @@ def minplus_gemm(A, B, C=None, check=True, cfg=-1, stream=None, d_status=None):
     if C is None:
         C = alloc_matrix(M, N, A.device)
     st = d_status if d_status is not None else (_status_tensor(A.device) if check else None)
-    _ok(lib().mpr_minplus_gemm_cfg(cfg, M, N, K, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C),
-                                   _ptr(st), _stream(stream)), "mpr_minplus_gemm")
+    fn = lib().mpr_minplus_gemm_spare if spare else lib().mpr_minplus_gemm_cfg
+    _ok(fn(cfg, M, N, K, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), _ptr(st), _stream(stream)),
+        "mpr_minplus_gemm")
     if check and d_status is None:
         check_status(st)
     return C

@@ -383,6 +383,22 @@ extern "C" mpr_status mpr_minplus_gemm_cfg(int cfg, int64_t M, int64_t N, int64_
     return gemm_launch(cfg, M, N, K, A, lda, B, ldb, C, ldc, s);
 }
 
+extern "C" mpr_status mpr_minplus_gemm_spare(int cfg, int64_t M, int64_t N, int64_t K, const uint16_t *A,
+                                             int64_t lda, const uint16_t *B, int64_t ldb, uint16_t *C, int64_t ldc,
+                                             int32_t *d_status, mpr_stream stream)
+{
+    mpr_status e = gemm_args(M, N, K, A, lda, B, ldb, C, ldc);
+    if (e != MPR_OK) return e;
+    if (cfg < -1 || cfg >= mpr_gemm_config_count()) return MPR_EINVAL;
+    if ((e = ensure_init()) != MPR_OK) return e;
+    hipStream_t s = as_stream(stream);
+    if (d_status) {
+        if ((e = validate_launch(A, M, K, lda, d_status, s)) != MPR_OK) return e;
+        if ((e = validate_launch(B, K, N, ldb, d_status, s)) != MPR_OK) return e;
+    }
+    return gemm_launch_spare(cfg, M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
 extern "C" mpr_status mpr_minplus_gemm(int64_t M, int64_t N, int64_t K, const uint16_t *A, int64_t lda,
                                        const uint16_t *B, int64_t ldb, uint16_t *C, int64_t ldc, int32_t *d_status,
                                        mpr_stream stream)

@@ -62,6 +62,8 @@ def test_argument_errors_are_synchronous(mpr):
     assert L.mpr_minplus_gemm(4, 4, 4, None, 4, None, 4, None, 4, None, None) == 1
     p = ctypes.c_void_p(16)
     assert L.mpr_minplus_gemm(4, 8, 4, p, 3, p, 8, p, 8, None, None) == 1
+    assert L.mpr_minplus_gemm_spare(-1, 4, 8, 4, p, 3, p, 8, p, 8, None, None) == 1
+    assert L.mpr_minplus_gemm_spare(99, 4, 8, 4, p, 4, p, 8, p, 8, None, None) == 1  # no such configuration
     assert L.mpr_minplus_power(p, 4, 4, 0, 0, p, 4, p, p, 1 << 20, None, None) == 1
     assert L.mpr_minplus_power(p, 4, 4, 3, 7, p, 4, p, p, 1 << 20, None, None) == 1
     assert L.mpr_minplus_power(p, 4, 4, 3, 0, p, 4, p, p, 16, None, None) == 2  # workspace too small

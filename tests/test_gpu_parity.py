@@ -51,6 +51,41 @@ def test_gemm_random_all_configs(mpr, shape):
         assert np.array_equal(_host(C), ref), cfg
 
 
+@pytest.mark.parametrize("law", [(0, 15, 0.30), (1024, 1039, 0.30)])
+def test_gemm_spare_grid_form_all_configs(mpr, law):
+    """The grid form (mpr_minplus_gemm_spare: at most 7/8 of the resident
+    workgroups, each looping over tiles) at a ragged size with more tiles
+    than that grid holds for every configuration (over 1000 of 64 x 64 and
+    128 x 128, over 500 of the larger tiles): the whole product equals the
+    one-block-per-tile launch bit for bit, and sampled rows (tile seams, the
+    last row) equal the oracle's.  The second entry law sends every tile of
+    the f16 configurations through their uint16 recomputation."""
+    M, N, K = 4001, 4103, 999
+    lo, hi, inf = law
+    print("gemm spare", law, flush=True)
+    X = synth.random_matrix(M, K, 111 + lo, lo, hi, inf)
+    Y = synth.random_matrix(K, N, 112 + lo, lo, hi, inf)
+    rows = [0, 1, 63, 64, 127, 128, 255, 256, 1999, 2048, M - 2, M - 1]
+    ref = _u16(O.minplus(O.from_u16(X[rows]), O.from_u16(Y)))
+    A, B = _dev(mpr, X), _dev(mpr, Y)
+    for cfg in range(mpr.gemm_config_count()):
+        C0 = mpr.minplus_gemm(A, B, cfg=cfg)
+        C1 = mpr.minplus_gemm(A, B, cfg=cfg, spare=True)
+        assert torch.equal(C0, C1), cfg
+        assert np.array_equal(_host(C1)[rows], ref), cfg
+
+
+def test_gemm_spare_small_takes_plain_launch(mpr):
+    """A product with fewer tiles than the grid form's grid is the plain
+    launch, same bits as the oracle."""
+    X = synth.random_matrix(130, 77, 121, 0, 15, 0.3)
+    Y = synth.random_matrix(77, 201, 122, 0, 15, 0.3)
+    ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
+    A, B = _dev(mpr, X), _dev(mpr, Y)
+    for cfg in range(mpr.gemm_config_count()):
+        assert np.array_equal(_host(mpr.minplus_gemm(A, B, cfg=cfg, spare=True)), ref), cfg
+
+
 def test_gemm_unaligned_leading_dimensions(mpr):
     """Row strides that are not multiples of 8 take the element-wise path."""
     M, N, K = 45, 37, 29
