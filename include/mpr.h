@@ -53,7 +53,9 @@ typedef enum {
     MPR_EOVERFLOW = 3,    /* finite value above MPR_FMAX would enter a product */
     MPR_ENOTFOUND = 4,    /* no periodic regime up to the requested power */
     MPR_EHIP = 5,         /* HIP runtime error */
-    MPR_EUNSUPPORTED = 6  /* no gfx950 device, or a size beyond the limits */
+    MPR_EUNSUPPORTED = 6, /* no gfx950 device, or a size beyond the limits */
+    MPR_ETIMEDOUT = 7,    /* query server: the request waited past its deadline */
+    MPR_ECANCELED = 8     /* query server: the request was cancelled */
 } mpr_status;
 
 #define MPR_INF 0xFFFFu
@@ -215,6 +217,25 @@ mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *
 mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t lda, int64_t e,
                              int schedule, uint16_t *N_out, int64_t ldo, int64_t *R_out,
                              void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream);
+
+/* Resumes a chain (Algorithm 2's step A^(k+1) = A^k (x) A, kept in
+ * canonical form as mpr_minplus_power does) from a power saved earlier:
+ * given (N_k, R_k), the canonical form of A^k (N_k n x n, row stride ldk,
+ * entries <= MPR_FMAX, e.g. copied back from a checkpoint on the host),
+ * writes the canonical form of A^(k + steps) to (N_out, R_out) by `steps`
+ * steps of the chain (schedule MPR_CHAIN or MPR_CHAIN_SPARSE), the same
+ * bits as mpr_minplus_power(A, k + steps) would give: row i of a power
+ * depends only on row i of the previous one and on A, so the state of a
+ * chain is (N_k, R_k, k).  steps = 0 copies.  N_out may be N_k (then
+ * ldo == ldk) and R_out may be R_k.  Workspace:
+ * mpr_power_workspace_size(n, steps + 1, schedule) bytes (for
+ * MPR_CHAIN_SPARSE the plan rules of mpr_minplus_power apply).  N_k is
+ * checked like A (d_status). */
+mpr_status mpr_chain_resume(const uint16_t *A, int64_t n, int64_t lda,
+                            const uint16_t *N_k, int64_t ldk, const int64_t *R_k,
+                            int64_t steps, int schedule, uint16_t *N_out, int64_t ldo,
+                            int64_t *R_out, void *ws, size_t ws_bytes,
+                            int32_t *d_status, mpr_stream stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
@@ -480,6 +501,10 @@ typedef struct {
                                  max_n) and frees its device memory; a query
                                  is a table read with no GPU work.  baby,
                                  wide_only, max_batch and slots are unused. */
+    double request_timeout_s; /* > 0: a request not yet launched this many
+                                 seconds after its submission (waiting for
+                                 its ladder, for memory or for a launch slot)
+                                 is completed with MPR_ETIMEDOUT; 0: none */
 } mpr_server_options;
 
 typedef struct {
@@ -524,6 +549,11 @@ mpr_status mpr_server_create(const mpr_server_options *opt, void **server_host);
  * ladder is larger than the whole budget with MPR_ENOMEM; a ladder whose
  * build fails completes its requests with the build's status. */
 mpr_status mpr_server_submit(void *server, int m, int64_t n, int64_t tag);
+/* Completes with MPR_ECANCELED every request with this tag that is still
+ * waiting (not yet in a launch) when the worker next looks; a request
+ * already launched or answered is not affected (its result comes as
+ * usual).  Asynchronous: the outcome arrives through mpr_server_poll. */
+mpr_status mpr_server_cancel(void *server, int64_t tag);
 /* Moves up to capacity finished requests into out_host (host array),
  * waiting up to wait_ms for the first one.  *count_host = number moved. */
 mpr_status mpr_server_poll(void *server, mpr_query_result *out_host, int capacity, int *count_host,

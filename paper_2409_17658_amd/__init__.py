@@ -55,7 +55,8 @@ class ChainDesc(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("baby", ctypes.c_int), ("max_n", ctypes.c_int64),
                 ("max_batch", ctypes.c_int), ("slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("wide_only", ctypes.c_int), ("busy_poll", ctypes.c_int), ("period_mode", ctypes.c_int)]
+                ("wide_only", ctypes.c_int), ("busy_poll", ctypes.c_int), ("period_mode", ctypes.c_int),
+                ("request_timeout_s", ctypes.c_double)]
 
 
 class QueryResult(ctypes.Structure):
@@ -93,6 +94,7 @@ _SIGS = {
                                    _P, _SZ, _P, _P]),
     "mpr_power_workspace_size": (_I, [_I64, _I64, _I, _P]),
     "mpr_minplus_power": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _SZ, _P, _P]),
+    "mpr_chain_resume": (_I, [_P, _I64, _I64, _P, _I64, _P, _I64, _I, _P, _I64, _P, _P, _SZ, _P, _P]),
     "mpr_minplus_power_noalloc": (_I, [_P, _I64, _I64, _I64, _I, _P, _I64, _P, _P, _P]),
     "mpr_sparse_plan_bytes": (_I, [_P, _I64, _I64, _P, _P]),
     "mpr_trace_min": (_I, [_P, _I64, _I64, _P, _P, _P]),
@@ -126,6 +128,7 @@ _SIGS = {
     "mpr_server_submit": (_I, [_P, _I, _I64, _I64]),
     "mpr_server_poll": (_I, [_P, _P, _I, _P, _I]),
     "mpr_server_stats_get": (_I, [_P, _P]),
+    "mpr_server_cancel": (_I, [_P, _I64]),
     "mpr_server_now": (ctypes.c_double, [_P]),
     "mpr_server_ladder_bytes": (_I64, [_I, _I, _I64, _I]),
     "mpr_server_period_bytes": (_I64, [_I]),
@@ -355,6 +358,44 @@ def minplus_power(A, e: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=N
     if check and d_status is None:
         check_status(st)
     return N_out, R_out
+
+
+def chain_resume(A, N_k, R_k, steps: int, schedule: int = CHAIN, N_out=None, R_out=None, ws=None, check=True,
+                 stream=None, d_status=None):
+    """Canonical form of A^(k + steps) from that of A^k, (N_k, R_k), by
+    `steps` chain steps (mpr_chain_resume)."""
+    n = A.shape[0]
+    if N_out is None:
+        N_out = alloc_matrix(n, n, A.device)
+    if R_out is None:
+        R_out = torch.empty(n, dtype=torch.int64, device=A.device)
+    st = d_status if d_status is not None else (_status_tensor(A.device) if check else None)
+    if ws is None:
+        if schedule == CHAIN_SPARSE and st is not None and steps >= 1:
+            ws = workspace(power_workspace_size(n, steps + 1, CHAIN) + 256 + sparse_plan_bytes(A, stream), A.device)
+        else:
+            ws = workspace(power_workspace_size(n, steps + 1, schedule), A.device)
+    _ok(lib().mpr_chain_resume(_ptr(A), n, _ld(A), _ptr(N_k), _ld(N_k), _vptr(R_k, n), steps, schedule, _ptr(N_out),
+                               _ld(N_out), _vptr(R_out, n), _ptr(ws), ws.numel(), _ptr(st), _stream(stream)),
+        "mpr_chain_resume")
+    if check and d_status is None:
+        check_status(st)
+    return N_out, R_out
+
+
+def save_power(path, N, R, k: int):
+    """Checkpoint of a chain: the canonical form (N, R) of A^k and k, written
+    to an .npz file (plain arrays, no pickled objects)."""
+    np.savez(path, N=to_host(N), R=R.cpu().numpy().astype(np.int64), k=np.int64(k))
+
+
+def load_power(path, device="cuda"):
+    """(N, R, k) of a checkpoint written by save_power, N and R on `device`."""
+    with np.load(path, allow_pickle=False) as z:
+        N, R, k = z["N"], z["R"], int(z["k"])
+    if N.dtype != np.uint16 or R.dtype != np.int64 or N.shape[0] != N.shape[1] or R.shape != (N.shape[0],):
+        raise ValueError("not a checkpoint of a canonical power")
+    return to_device(N, device), torch.from_numpy(R).to(device), k
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

@@ -173,15 +173,28 @@ static PowerWs carve_power(void *ws, int64_t n, int schedule, size_t ws_bytes = 
     return w;
 }
 
+// e - 1 chain steps from a first power: A itself (normalised), or, when N0
+// is given, the canonical form (N0, R0) of a power saved earlier, so a chain
+// resumes where it stopped (row i of the next power needs row i of this one
+// and A only).
 static mpr_status power_chain(const u16 *A, int64_t n, int64_t lda, int64_t e, u16 *N_out, int64_t ldo,
-                              int64_t *R_out, const PowerWs &w, int32_t *st, hipStream_t s, bool sparse)
+                              int64_t *R_out, const PowerWs &w, int32_t *st, hipStream_t s, bool sparse,
+                              const u16 *N0 = nullptr, const int64_t *R0 = nullptr, int64_t ld0 = 0)
 {
     // Step k writes buffer (e - k) % 2, so step e lands in N_out.
     u16 *buf[2] = {N_out, w.P};
     const int64_t ld[2] = {ldo, w.ld};
     int b = (int)((e - 1) & 1);
-    mpr_status r = copy_launch(A, lda, buf[b], ld[b], n, n, s);
-    if (r == MPR_OK) r = normalise_launch(n, n, buf[b], ld[b], nullptr, nullptr, R_out, st, nullptr, s);
+    mpr_status r;
+    if (N0) {
+        r = N0 == buf[b] ? MPR_OK : copy_launch(N0, ld0, buf[b], ld[b], n, n, s);
+        if (r == MPR_OK && R0 != R_out &&
+            hipMemcpyAsync(R_out, R0, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            r = MPR_EHIP;
+    } else {
+        r = copy_launch(A, lda, buf[b], ld[b], n, n, s);
+        if (r == MPR_OK) r = normalise_launch(n, n, buf[b], ld[b], nullptr, nullptr, R_out, st, nullptr, s);
+    }
     if (r == MPR_OK && sparse && e >= 2) r = sparse_plan_launch(A, n, lda, w.plan, w.plan_bytes, st, s);
     for (int64_t k = 2; k <= e && r == MPR_OK; k++) {
         const int nb = b ^ 1;
@@ -310,6 +323,8 @@ extern "C" const char *mpr_status_string(int status)
     case MPR_ENOTFOUND: return "no periodic regime found";
     case MPR_EHIP: return "HIP runtime error";
     case MPR_EUNSUPPORTED: return "unsupported device or size";
+    case MPR_ETIMEDOUT: return "request waited past its deadline";
+    case MPR_ECANCELED: return "request cancelled";
     default: return "unknown status";
     }
 }
@@ -474,6 +489,30 @@ extern "C" mpr_status mpr_minplus_power(const uint16_t *A, int64_t n, int64_t ld
     if ((r = validate_launch(A, n, n, lda, d_status, s)) != MPR_OK) return r;
     if (schedule == MPR_SQUARE) return power_square(A, n, lda, e, N_out, ldo, R_out, w, d_status, s);
     return power_chain(A, n, lda, e, N_out, ldo, R_out, w, d_status, s, schedule == MPR_CHAIN_SPARSE);
+}
+
+extern "C" mpr_status mpr_chain_resume(const uint16_t *A, int64_t n, int64_t lda, const uint16_t *N_k, int64_t ldk,
+                                       const int64_t *R_k, int64_t steps, int schedule, uint16_t *N_out, int64_t ldo,
+                                       int64_t *R_out, void *ws, size_t ws_bytes, int32_t *d_status, mpr_stream stream)
+{
+    if (n < 0 || steps < 0 || (schedule != MPR_CHAIN && schedule != MPR_CHAIN_SPARSE)) return MPR_EINVAL;
+    if (n && (!A || !N_k || !R_k || !N_out || !R_out)) return MPR_EINVAL;
+    if (!ld_ok(lda, n) || !ld_ok(ldk, n) || !ld_ok(ldo, n)) return MPR_EINVAL;
+    if (N_k == N_out && ldk != ldo) return MPR_EINVAL;
+    if (n == 0) return MPR_OK;
+    PowerWs w = carve_power(ws, n, schedule, ws_bytes);
+    if (!ws || ws_bytes < w.bytes) return MPR_ENOMEM;
+    if (schedule == MPR_CHAIN_SPARSE && !w.plan_full) {
+        if (w.plan_bytes < sparse_plan_bytes_rows(n, 0)) return MPR_ENOMEM;
+        if (!d_status) return MPR_EINVAL;
+    }
+    mpr_status r = ensure_init();
+    if (r != MPR_OK) return r;
+    hipStream_t s = as_stream(stream);
+    if ((r = validate_launch(A, n, n, lda, d_status, s)) != MPR_OK) return r;
+    if ((r = validate_launch(N_k, n, n, ldk, d_status, s)) != MPR_OK) return r;
+    return power_chain(A, n, lda, steps + 1, N_out, ldo, R_out, w, d_status, s, schedule == MPR_CHAIN_SPARSE, N_k, R_k,
+                       ldk);
 }
 
 extern "C" mpr_status mpr_minplus_power_noalloc(const uint16_t *A, int64_t n, int64_t lda, int64_t e, int schedule,

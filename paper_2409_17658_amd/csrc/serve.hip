@@ -307,6 +307,7 @@ struct Server {
     std::mutex mu;
     std::condition_variable cv_in, cv_out;
     std::deque<Request> inbox;
+    std::vector<int64_t> cancels;  // tags to cancel (mpr_server_cancel)
     std::deque<mpr_query_result> outbox;
     bool stop = false;
     std::thread worker;
@@ -788,6 +789,7 @@ static void worker_main(Server *Sp)
     const int B = S.opt.baby;
     for (;;) {
         std::vector<Request> fresh;
+        std::vector<int64_t> cancels;
         {
             std::unique_lock<std::mutex> lk(S.mu);
             // A finished query launch is seen on the next pass, so the wait is
@@ -797,7 +799,7 @@ static void worker_main(Server *Sp)
             for (auto &sl : S.slots) queries |= sl.busy;
             for (auto &kv : S.ladders) other |= kv.second.state == Ladder::BUILDING;
             const int wait_us = queries ? 5 : other ? 50 : 2000;
-            if (S.inbox.empty() && !S.stop) {
+            if (S.inbox.empty() && S.cancels.empty() && !S.stop) {
                 if (S.opt.busy_poll) {
                     lk.unlock();
                     std::this_thread::yield();
@@ -811,6 +813,26 @@ static void worker_main(Server *Sp)
                 fresh.push_back(S.inbox.front());
                 S.inbox.pop_front();
             }
+            cancels.swap(S.cancels);
+        }
+        // 0. cancellations and deadlines of requests not yet launched
+        if (!cancels.empty() || S.opt.request_timeout_s > 0) {
+            const double now = S.now(), limit = S.opt.request_timeout_s;
+            auto drop = [&](const Request &r) {
+                if (std::find(cancels.begin(), cancels.end(), r.tag) != cancels.end()) {
+                    complete(S, r, ROW_NONE, MPR_ECANCELED, now);
+                    return true;
+                }
+                if (limit > 0 && now - r.t_submit > limit) {
+                    complete(S, r, ROW_NONE, MPR_ETIMEDOUT, now);
+                    return true;
+                }
+                return false;
+            };
+            fresh.erase(std::remove_if(fresh.begin(), fresh.end(), drop), fresh.end());
+            for (auto &kv : S.waiting) kv.second.erase(std::remove_if(kv.second.begin(), kv.second.end(), drop),
+                                                       kv.second.end());
+            cancels.clear();
         }
         // 1. retire finished batches
         for (auto &sl : S.slots) {
@@ -1083,6 +1105,18 @@ extern "C" mpr_status mpr_server_submit(void *server, int m, int64_t n, int64_t 
         std::lock_guard<std::mutex> lk(S->mu);
         S->inbox.push_back(r);
         S->stats.submitted++;
+    }
+    S->cv_in.notify_one();
+    return MPR_OK;
+}
+
+extern "C" mpr_status mpr_server_cancel(void *server, int64_t tag)
+{
+    Server *S = (Server *)server;
+    if (!S) return MPR_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->cancels.push_back(tag);
     }
     S->cv_in.notify_one();
     return MPR_OK;

@@ -16,9 +16,9 @@ from . import MprError, QueryResult, ServerOptions, ServerStats, lib
 class Server:
     def __init__(self, device: int = 0, baby: int = 32, max_n: int = 1000, max_batch: int = 256,
                  slots: int = 4, hbm_budget_bytes: int = 200 << 30, wide_only: bool = False,
-                 busy_poll: bool = False, period_mode: bool = False):
+                 busy_poll: bool = False, period_mode: bool = False, request_timeout_s: float = 0.0):
         self.opt = ServerOptions(device, baby, max_n, max_batch, slots, hbm_budget_bytes, int(bool(wide_only)),
-                                 int(bool(busy_poll)), int(bool(period_mode)))
+                                 int(bool(busy_poll)), int(bool(period_mode)), float(request_timeout_s))
         h = ctypes.c_void_p()
         st = lib().mpr_server_create(ctypes.byref(self.opt), ctypes.byref(h))
         if st != 0:
@@ -31,6 +31,12 @@ class Server:
         st = lib().mpr_server_submit(self.h, m, n, tag)
         if st != 0:
             raise MprError(st, "mpr_server_submit")
+
+    def cancel(self, tag: int):
+        """Requests with this tag still waiting complete with MPR_ECANCELED."""
+        st = lib().mpr_server_cancel(self.h, tag)
+        if st != 0:
+            raise MprError(st, "mpr_server_cancel")
 
     def poll(self, wait_ms: int = 10):
         if self._held:

@@ -68,9 +68,16 @@ def test_argument_errors_are_synchronous(mpr):
     assert L.mpr_minplus_power(p, 4, 4, 3, 7, p, 4, p, p, 1 << 20, None, None) == 1
     assert L.mpr_minplus_power(p, 4, 4, 3, 0, p, 4, p, p, 16, None, None) == 2  # workspace too small
     assert L.mpr_build_transfer(12, p, 1 << 20, None) == 1
+    # chain_resume: squaring is not a chain, negative steps, in place with another stride
+    assert L.mpr_chain_resume(p, 4, 8, p, 8, p, 3, 1, p, 8, p, p, 1 << 20, None, None) == 1
+    assert L.mpr_chain_resume(p, 4, 8, p, 8, p, -1, 0, p, 8, p, p, 1 << 20, None, None) == 1
+    assert L.mpr_chain_resume(p, 4, 8, p, 8, p, 3, 0, p, 16, p, p, 1 << 20, None, None) == 1
+    assert L.mpr_chain_resume(p, 4, 8, p, 8, p, 3, 0, ctypes.c_void_p(32), 8, p, p, 16, None, None) == 2
     assert L.mpr_batch_launch(ctypes.c_void_p(12345), None, None) == 1  # never planned
     assert L.mpr_graph_launch(None, None) == 1
     assert mpr.lib().mpr_status_string(3).decode().startswith("finite value")
+    assert mpr.lib().mpr_status_string(7).decode().startswith("request waited")
+    assert mpr.lib().mpr_status_string(8).decode() == "request cancelled"
 
 
 def test_workspace_sizes(mpr):

@@ -273,6 +273,46 @@ def test_cold_ladder_answers_progressively(serve):
     assert st["early_answers"] >= 3 and st["builds"] == 1
 
 
+def test_server_request_deadline(serve):
+    """Requests not launched within request_timeout_s complete with
+    MPR_ETIMEDOUT (7): a cold m = 8 query for n = 999 needs the ladder's last
+    giant, which takes longer than 20 ms to build; once the ladder is
+    resident the same query is answered within the deadline."""
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=4, hbm_budget_bytes=200 << 30,
+                      request_timeout_s=0.02) as S:
+        r = S.query(8, 999)
+        assert r["status"] == 7 and r["t_done"] - r["t_submit"] >= 0.02
+        t_end = time.monotonic() + 60
+        while S.stats()["narrow_builds"] < 1 and time.monotonic() < t_end:
+            time.sleep(0.01)
+        r2 = S.query(8, 999)
+        st = S.stats()
+    assert r2["status"] == 0 and r2["gamma"] == golden_gamma(8, 999)
+    assert st["builds"] == 1
+
+
+def test_server_cancel(serve):
+    """mpr_server_cancel completes a waiting request with MPR_ECANCELED (8);
+    requests of other tags, and a cancel of an unknown tag, are unaffected."""
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=4, hbm_budget_bytes=200 << 30) as S:
+        S.submit(8, 999, 1)
+        S.submit(8, 998, 2)
+        S.cancel(1)
+        S.cancel(12345)
+        got, t_end = {}, time.monotonic() + 60
+        while len(got) < 2 and time.monotonic() < t_end:
+            for r in S.poll(20):
+                got[r["tag"]] = r
+        r3 = S.query(8, 997)
+        S.cancel(2)  # already answered: nothing happens
+        time.sleep(0.05)
+        late = S.poll(0)
+    assert got[1]["status"] == 8
+    assert got[2]["status"] == 0 and got[2]["gamma"] == golden_gamma(8, 998)
+    assert r3["status"] == 0 and r3["gamma"] == golden_gamma(8, 997)
+    assert late == []
+
+
 def test_build_refused_without_free_memory_then_retried(serve):
     """Admission is by the device's free memory as well as the byte budget:
     with almost all of the device's memory held elsewhere (a host-side
