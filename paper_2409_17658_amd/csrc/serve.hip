@@ -102,7 +102,7 @@ __device__ __forceinline__ void tr8_group_rows(const TRDesc *__restrict__ g, int
             uint4 a[TR_TRIP];
 #pragma unroll
             for (int k = 0; k < TR_TRIP; k++)
-                a[k] = c + k * 1024 < n16 ? gload16((const gu16 *)(gx + c + k * 1024)) : inf;
+                a[k] = c + k * 1024 < n16 ? gload16_nt((const gu16 *)(gx + c + k * 1024)) : inf;
 #pragma unroll
             for (int q = 0; q < TR_GROUP; q++) {
                 if (q >= nq) break;  // uniform
@@ -110,7 +110,7 @@ __device__ __forceinline__ void tr8_group_rows(const TRDesc *__restrict__ g, int
                 uint4 b[TR_TRIP];
 #pragma unroll
                 for (int k = 0; k < TR_TRIP; k++)
-                    b[k] = c + k * 1024 < n16 ? gload16((const gu16 *)(gy + c + k * 1024)) : inf;
+                    b[k] = c + k * 1024 < n16 ? gload16_nt((const gu16 *)(gy + c + k * 1024)) : inf;
 #pragma unroll
                 for (int k = 0; k < TR_TRIP; k++) best[q] = tr8_min16(a[k], b[k], best[q]);
             }

