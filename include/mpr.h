@@ -154,14 +154,16 @@ mpr_status mpr_minplus_gemm_cfg(int cfg, int64_t M, int64_t N, int64_t K,
                                 uint16_t *C, int64_t ldc,
                                 int32_t *d_status, mpr_stream stream);
 
-/* The same product (same configurations, same bits) from a grid of at most
- * 7/8 of the device's resident workgroups of the configuration, each looping
- * over tiles, so that work on other streams finds free workgroup slots for
- * as long as the product runs (without it a long product holds every slot
- * until its blocks retire).  For callers that run long products beside
+/* The same product (same bits) launched so that each CU holds one
+ * workgroup of it fewer than it could: every workgroup reserves extra LDS,
+ * so the registers of one workgroup slot per CU stay free for the waves of
+ * other launches for as long as the product runs (without it a long
+ * product holds every slot until its blocks retire, milliseconds each).  A
+ * configuration that fits fewer than 3 workgroups per CU runs as the
+ * 128 x 128 tile of the same arithmetic.  Costs well under 1 % at the sizes
+ * measured (N = 7411 to 21909).  For callers that run long products beside
  * latency-sensitive work: the query server builds its large ladders with
- * it.  Products with fewer tiles than the grid take the plain launch.
- * cfg = -1 picks from the tile table.  Arguments and errors as
+ * it.  cfg = -1 picks from the tile table.  Arguments and errors as
  * mpr_minplus_gemm. */
 mpr_status mpr_minplus_gemm_spare(int cfg, int64_t M, int64_t N, int64_t K,
                                   const uint16_t *A, int64_t lda,

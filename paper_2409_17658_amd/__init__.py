@@ -285,8 +285,8 @@ def build_border_transfer(m: int, out=None, stream=None):
 
 
 def minplus_gemm(A, B, C=None, check=True, cfg=-1, stream=None, d_status=None, spare=False):
-    """C = A (x) B.  spare=True: the grid form that leaves an eighth of the
-    device's workgroup slots free while it runs (same bits)."""
+    """C = A (x) B.  spare=True: the launch that leaves one workgroup slot
+    per CU free for other launches while it runs (same bits)."""
     M, K = A.shape
     K2, N = B.shape
     if K != K2:

@@ -128,8 +128,9 @@ int device_cu_count();
 // gemm.hip
 mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda,
                        const u16 *B, int64_t ldb, u16 *C, int64_t ldc, hipStream_t s);
-// The same product from at most 7/8 of the device's resident workgroups, so
-// that work on other streams finds free slots while it runs.
+// The same product holding one workgroup per CU fewer than it could (extra
+// LDS per workgroup), so that work on other streams finds free slots while
+// it runs.
 mpr_status gemm_launch_spare(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda,
                              const u16 *B, int64_t ldb, u16 *C, int64_t ldc, hipStream_t s);
 int pick_config(int64_t M, int64_t N, int64_t K);

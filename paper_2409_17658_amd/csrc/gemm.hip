@@ -23,9 +23,10 @@ using Cfg6 = TileCfg<256, 128, 32, 8, 8>;    // 512 threads, 8x8 per lane
 // Renumber so that each XCD receives a contiguous run of tiles, and walk the
 // tiles in groups of G tile-rows so that the blocks resident on one XCD share
 // A row panels and B column panels in that XCD's L2.
-__device__ __forceinline__ bool tile_of(int b, int nb, int tiles_m, int tiles_n, int &tm, int &tn)
+__device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
 {
-    // nb: a multiple of 8
+    const int nb = (int)gridDim.x;  // a multiple of 8
+    const int b = (int)blockIdx.x;
     const int t = (b & 7) * (nb >> 3) + (b >> 3);
     if (t >= tiles_m * tiles_n) return false;
     constexpr int G = 8;
@@ -36,10 +37,6 @@ __device__ __forceinline__ bool tile_of(int b, int nb, int tiles_m, int tiles_n,
     tm = first + w % gs;
     tn = w / gs;
     return true;
-}
-__device__ __forceinline__ bool tile_of_block(int tiles_m, int tiles_n, int &tm, int &tn)
-{
-    return tile_of((int)blockIdx.x, (int)gridDim.x, tiles_m, tiles_n, tm, tn);
 }
 
 // Waves per SIMD the register allocation must allow: 4 (<= 128 VGPRs) for
@@ -64,29 +61,6 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(GemmWaves
     tile_store<T>(C, ldc, M, N, m0, n0, vec != 0, acc);
 }
 
-// The same product from a grid smaller than its block count: block b takes
-// the tiles of virtual blocks b, b + grid, ... of a virtual grid of
-// `vblocks` (both multiples of 8, so a virtual block runs on the XCD it
-// would have run on in the one-block-per-tile launch).  A grid below the
-// device's resident capacity leaves workgroup slots free for other work for
-// as long as the product runs.
-template <class T, bool H>
-__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value))) void gemm_grid_kernel(
-    const u16 *__restrict__ A, int64_t lda, const u16 *__restrict__ B, int64_t ldb, u16 *__restrict__ C, int64_t ldc,
-    int64_t M, int64_t N, int64_t K, int tiles_m, int tiles_n, int vec, int vblocks)
-{
-    __shared__ __attribute__((aligned(16))) u16 lds[T::LDS_ELEMS];
-    for (int vb = (int)blockIdx.x; vb < vblocks; vb += (int)gridDim.x) {  // block-uniform
-        int tm, tn;
-        if (!tile_of(vb, vblocks, tiles_m, tiles_n, tm, tn)) continue;
-        const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
-        TileAcc<T> acc;
-        tile_mainloop<T, H>(A, lda, B, ldb, M, N, K, m0, n0, vec != 0, lds, acc);
-        tile_store<T>(C, ldc, M, N, m0, n0, vec != 0, acc);
-        __syncthreads();  // the next tile refills lds
-    }
-}
-
 // An empty inner dimension: every entry of C is infinite.
 __global__ void fill_inf_kernel(u16 *C, int64_t ldc, int64_t M, int64_t N)
 {
@@ -97,56 +71,38 @@ __global__ void fill_inf_kernel(u16 *C, int64_t ldc, int64_t M, int64_t N)
 
 template <class T, bool H>
 static mpr_status launch_cfg(int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
-                             int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
+                             int64_t ldb, u16 *C, int64_t ldc, hipStream_t s, size_t pad_lds = 0)
 {
     const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
     const int64_t tiles = tiles_m * tiles_n;
     if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
     const int64_t blocks = round_up(tiles, 8);
     const bool vec = aligned16(A) && aligned16(B) && aligned16(C) && lda % 8 == 0 && ldb % 8 == 0 && ldc % 8 == 0;
-    hipLaunchKernelGGL((gemm_kernel<T, H>), dim3((unsigned)blocks), dim3(T::NT), 0, s, A, lda, B, ldb, C, ldc, M, N, K,
-                       (int)tiles_m, (int)tiles_n, vec ? 1 : 0);
+    hipLaunchKernelGGL((gemm_kernel<T, H>), dim3((unsigned)blocks), dim3(T::NT), pad_lds, s, A, lda, B, ldb, C, ldc, M,
+                       N, K, (int)tiles_m, (int)tiles_n, vec ? 1 : 0);
     return check_launch();
 }
 
-// The grid form with at most max_blocks blocks (a multiple of 8); the
-// one-block-per-tile launch when the tiles fit in it.
+// Workgroups of a configuration resident per CU, and its static LDS bytes.
 template <class T, bool H>
-static mpr_status launch_cfg_grid(int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
-                                  int64_t ldb, u16 *C, int64_t ldc, int max_blocks, hipStream_t s)
-{
-    const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
-    const int64_t tiles = tiles_m * tiles_n;
-    if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
-    const int64_t blocks = round_up(tiles, 8);
-    if (max_blocks < 8 || blocks <= max_blocks) return launch_cfg<T, H>(M, N, K, A, lda, B, ldb, C, ldc, s);
-    const bool vec = aligned16(A) && aligned16(B) && aligned16(C) && lda % 8 == 0 && ldb % 8 == 0 && ldc % 8 == 0;
-    hipLaunchKernelGGL((gemm_grid_kernel<T, H>), dim3((unsigned)(max_blocks & ~7)), dim3(T::NT), 0, s, A, lda, B, ldb,
-                       C, ldc, M, N, K, (int)tiles_m, (int)tiles_n, vec ? 1 : 0, (int)blocks);
-    return check_launch();
-}
-
-// Workgroups of the grid form resident per CU.
-template <class T, bool H>
-static int grid_occupancy()
+static void residency(int *blocks, size_t *lds)
 {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)gemm_grid_kernel<T, H>, T::NT, 0) !=
-            hipSuccess ||
-        b < 1) {
+    hipFuncAttributes fa{};
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)gemm_kernel<T, H>, T::NT, 0) != hipSuccess ||
+        hipFuncGetAttributes(&fa, (const void *)gemm_kernel<T, H>) != hipSuccess) {
         (void)hipGetLastError();
-        b = 1;
+        b = 0;
     }
-    return b;
+    *blocks = b;
+    *lds = fa.sharedSizeBytes;
 }
 
 struct CfgInfo {
     int bm, bn, bk, tm, tn, nt, arith;
     mpr_status (*launch)(int64_t, int64_t, int64_t, const u16 *, int64_t, const u16 *, int64_t, u16 *, int64_t,
-                         hipStream_t);
-    mpr_status (*launch_grid)(int64_t, int64_t, int64_t, const u16 *, int64_t, const u16 *, int64_t, u16 *,
-                              int64_t, int, hipStream_t);
-    int (*occupancy)();
+                         hipStream_t, size_t);
+    void (*residency)(int *, size_t *);
 };
 
 // Configurations 0..5 compute in uint16 (MPR_ARITH_U16); 6..11 are the
@@ -155,7 +111,7 @@ struct CfgInfo {
 // 512-thread tile in uint16, 13 the same in the f16 form.
 #define MPR_CFG(T, H)                                                                                 \
     {T::BM, T::BN, T::BK, T::TM, T::TN, T::NT, H ? MPR_ARITH_F16 : MPR_ARITH_U16, launch_cfg<T, H>,       \
-     launch_cfg_grid<T, H>, grid_occupancy<T, H>}
+     residency<T, H>}
 static const CfgInfo kCfgs[] = {MPR_CFG(Cfg0, false), MPR_CFG(Cfg1, false), MPR_CFG(Cfg2, false),
                                 MPR_CFG(Cfg3, false), MPR_CFG(Cfg4, false), MPR_CFG(Cfg5, false),
                                 MPR_CFG(Cfg0, true),  MPR_CFG(Cfg1, true),  MPR_CFG(Cfg2, true),
@@ -201,8 +157,11 @@ mpr_status gemm_launch(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, i
     }
     if (cfg < 0) cfg = pick_config(M, N, K);
     if (cfg >= kNumCfgs) return MPR_EINVAL;
-    return kCfgs[cfg].launch(M, N, K, A, lda, B, ldb, C, ldc, s);
+    return kCfgs[cfg].launch(M, N, K, A, lda, B, ldb, C, ldc, s, 0);
 }
+
+// LDS of one CU on gfx950.
+constexpr size_t kLdsPerCU = 160 * 1024;
 
 mpr_status gemm_launch_spare(int cfg, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
                              int64_t ldb, u16 *C, int64_t ldc, hipStream_t s)
@@ -210,12 +169,36 @@ mpr_status gemm_launch_spare(int cfg, int64_t M, int64_t N, int64_t K, const u16
     if (M == 0 || N == 0 || K == 0) return gemm_launch(cfg, M, N, K, A, lda, B, ldb, C, ldc, s);
     if (cfg < 0) cfg = pick_config(M, N, K);
     if (cfg >= kNumCfgs) return MPR_EINVAL;
-    static std::atomic<int> occ[kNumCfgs];  // 0: not yet asked
-    int o = occ[cfg].load();
-    if (o == 0) occ[cfg] = o = kCfgs[cfg].occupancy();
-    const int64_t cap = (int64_t)o * device_cu_count();
-    const int max_blocks = (int)std::min<int64_t>(INT32_MAX, cap * 7 / 8) & ~7;
-    return kCfgs[cfg].launch_grid(M, N, K, A, lda, B, ldb, C, ldc, max_blocks, s);
+    // The plain launch, with extra dynamic LDS per workgroup so that one
+    // workgroup fewer fits on a CU than registers and static LDS allow: the
+    // blocks still retire and refill as usual, and the slot left over (its
+    // registers, and a few KB of LDS) takes the waves of other launches.  A
+    // configuration of fewer than 3 workgroups per CU gives way to the
+    // 128 x 128 tile of the same arithmetic (4 per CU).
+    static std::atomic<int> res_blocks[kNumCfgs];   // 0: not yet asked
+    static std::atomic<size_t> res_lds[kNumCfgs];
+    auto info = [&](int c, int &blocks, size_t &lds) {
+        blocks = res_blocks[c].load();
+        if (blocks == 0) {
+            size_t l = 0;
+            kCfgs[c].residency(&blocks, &l);
+            res_lds[c] = l;
+            res_blocks[c] = blocks > 0 ? blocks : -1;
+        }
+        lds = res_lds[c].load();
+    };
+    int blocks = 0;
+    size_t lds = 0;
+    info(cfg, blocks, lds);
+    if (blocks < 3) {
+        cfg = kCfgs[cfg].arith == MPR_ARITH_F16 ? 6 : 0;  // Cfg0 in either arithmetic
+        info(cfg, blocks, lds);
+    }
+    if (blocks < 3) return kCfgs[cfg].launch(M, N, K, A, lda, B, ldb, C, ldc, s, 0);
+    // (blocks - 1) workgroups of `per` bytes fit with 4 KB to spare, blocks do not
+    const size_t per = ((kLdsPerCU - 4096) / (size_t)(blocks - 1)) & ~(size_t)1023;
+    const size_t pad = per > lds ? per - lds : 0;
+    return kCfgs[cfg].launch(M, N, K, A, lda, B, ldb, C, ldc, s, pad);
 }
 
 }  // namespace mpr
@@ -292,9 +275,9 @@ extern "C" mpr_status mpr_autotune_gemm(int64_t n, int reps, float *ms_host, int
     float best = 1e30f;
     int besti = -1;
     for (int c = 0; c < kNumCfgs && st == MPR_OK; c++) {
-        st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s);  // warm-up
+        st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s, 0);  // warm-up
         hipEventRecord(e0, s);
-        for (int r = 0; r < reps && st == MPR_OK; r++) st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s);
+        for (int r = 0; r < reps && st == MPR_OK; r++) st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s, 0);
         hipEventRecord(e1, s);
         hipEventSynchronize(e1);
         float ms = 0.f;

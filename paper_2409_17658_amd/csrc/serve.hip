@@ -488,8 +488,8 @@ static mpr_status enqueue_giants(Server &S, Ladder &L, int upto)
     mpr_status e = MPR_OK;
     for (; !L.failing && L.next_giant <= std::min(upto, G) && e == MPR_OK; L.next_giant++) {
         const int i = L.next_giant;
-        // large products leave an eighth of the device's workgroup slots to
-        // the queries that run beside the build
+        // large products leave one workgroup slot per CU to the queries
+        // that run beside the build
         e = n >= kBigLadder ? gemm_launch_spare(-1, n, n, n, L.Ng[i - 1], ld, L.Bp, ld, L.Ng[i], ld, s)
                             : gemm_launch(-1, n, n, n, L.Ng[i - 1], ld, L.Bp, ld, L.Ng[i], ld, s);
         if (e == MPR_OK)

@@ -53,13 +53,14 @@ def test_gemm_random_all_configs(mpr, shape):
 
 @pytest.mark.parametrize("law", [(0, 15, 0.30), (1024, 1039, 0.30)])
 def test_gemm_spare_grid_form_all_configs(mpr, law):
-    """The grid form (mpr_minplus_gemm_spare: at most 7/8 of the resident
-    workgroups, each looping over tiles) at a ragged size with more tiles
-    than that grid holds for every configuration (over 1000 of 64 x 64 and
-    128 x 128, over 500 of the larger tiles): the whole product equals the
-    one-block-per-tile launch bit for bit, and sampled rows (tile seams, the
-    last row) equal the oracle's.  The second entry law sends every tile of
-    the f16 configurations through their uint16 recomputation."""
+    """The launch that leaves a workgroup slot per CU free
+    (mpr_minplus_gemm_spare: extra LDS per workgroup; configurations of
+    fewer than 3 workgroups per CU run as the 128 x 128 tile) at a ragged
+    size with more tiles than the device holds at once, for every
+    configuration: the whole product equals the plain launch bit for bit,
+    and sampled rows (tile seams, the last row) equal the oracle's.  The
+    second entry law sends every tile of the f16 configurations through
+    their uint16 recomputation."""
     M, N, K = 4001, 4103, 999
     lo, hi, inf = law
     print("gemm spare", law, flush=True)
@@ -75,9 +76,8 @@ def test_gemm_spare_grid_form_all_configs(mpr, law):
         assert np.array_equal(_host(C1)[rows], ref), cfg
 
 
-def test_gemm_spare_small_takes_plain_launch(mpr):
-    """A product with fewer tiles than the grid form's grid is the plain
-    launch, same bits as the oracle."""
+def test_gemm_spare_small(mpr):
+    """A small product in the same launch form, same bits as the oracle."""
     X = synth.random_matrix(130, 77, 121, 0, 15, 0.3)
     Y = synth.random_matrix(77, 201, 122, 0, 15, 0.3)
     ref = _u16(O.minplus(O.from_u16(X), O.from_u16(Y)))
