@@ -269,28 +269,30 @@ extern "C" mpr_status mpr_autotune_gemm(int64_t n, int reps, float *ms_host, int
     if (hipMalloc(&buf, (size_t)(3 * n * ld) * sizeof(u16)) != hipSuccess) return MPR_ENOMEM;
     u16 *A = buf, *B = buf + n * ld, *C = buf + 2 * n * ld;
     hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, buf, 2 * n * ld, (uint64_t)n);
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    st = check_launch();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == MPR_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = MPR_EHIP;
     float best = 1e30f;
     int besti = -1;
     for (int c = 0; c < kNumCfgs && st == MPR_OK; c++) {
         st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s, 0);  // warm-up
-        hipEventRecord(e0, s);
+        if (st == MPR_OK && hipEventRecord(e0, s) != hipSuccess) st = MPR_EHIP;
         for (int r = 0; r < reps && st == MPR_OK; r++) st = kCfgs[c].launch(n, n, n, A, ld, B, ld, C, ld, s, 0);
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (st == MPR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = MPR_EHIP;
+        if (st != MPR_OK) break;
         ms_host[c] = ms / reps;
         if (ms_host[c] < best) {
             best = ms_host[c];
             besti = c;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(buf);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);  // nothing of the timing still reads buf
+    (void)hipFree(buf);
     if (best_host) *best_host = besti;
     return st;
 }

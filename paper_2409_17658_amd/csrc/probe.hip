@@ -109,10 +109,10 @@ extern "C" mpr_status mpr_valu_probe(int arith, int iters, double *pairs_per_s_h
     st = MPR_EHIP;
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
         hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, 1u, iters / 8 + 1, sink, clk);  // warm-up
-        hipEventRecord(e0, s);
+        const bool rec0 = hipEventRecord(e0, s) == hipSuccess;
         hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, 2u, iters, sink, clk);
-        hipEventRecord(e1, s);
-        if (check_launch() == MPR_OK && hipEventSynchronize(e1) == hipSuccess &&
+        const bool rec1 = hipEventRecord(e1, s) == hipSuccess;
+        if (rec0 && rec1 && check_launch() == MPR_OK && hipEventSynchronize(e1) == hipSuccess &&
             hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
             hipMemcpy(host_clk, clk, sizeof(host_clk), hipMemcpyDeviceToHost) == hipSuccess && ms > 0.f &&
             host_clk[1] > 0)
