@@ -699,11 +699,12 @@ def leg_config1(mpr, torch):
 
     m, kmax = 3, 40
 
-    def gpu():
+    def gpu(pipeline=False):
         A = mpr.build_transfer(m)
-        return mpr.find_period(A, kmax, traces=True, slots=8)
+        return mpr.find_period(A, kmax, traces=True, slots=8, pipeline=pipeline)
 
     (mu, lam, c, tr), t_gpu = _timed(torch, gpu)
+    (mup, lamp, cp, trp), t_gpu_p = _timed(torch, lambda: gpu(True))
     t0 = time.perf_counter()
     Ao = O.transfer(m)
     g = {}
@@ -713,7 +714,10 @@ def leg_config1(mpr, torch):
     t_cpu = time.perf_counter() - t0
     ok = all(int(tr[n]) == g[n] for n in range(3, kmax + 1)) and all(int(tr[n]) == v for n, v in brute.items())
     return {"workload": "m=3 transfer matrix (33 states), gamma_R(P_3 x C_n) for n=3..40, period",
-            "period": [mu, lam, c], "gpu_s": round(t_gpu, 4), "gamma_3_40": [int(tr[n]) for n in range(3, kmax + 1)],
+            "period": [mu, lam, c], "gpu_s": round(t_gpu, 4),
+            "gpu_pipelined_s": round(t_gpu_p, 4),
+            "pipelined_same": bool((mup, lamp, cp) == (mu, lam, c) and np.array_equal(trp, tr)),
+            "gamma_3_40": [int(tr[n]) for n in range(3, kmax + 1)],
             "matches_oracle": bool(ok and tuple(per) == (mu, lam, c)),
             "cpu_baseline": {"value": round(t_cpu, 3), "unit": "s", "cores": O.threads(), "kind": "oracle",
                              "sample": "the whole config: chain to n=40, period, exhaustive search n=3..5"}}
@@ -798,6 +802,11 @@ def leg_config3(mpr, torch, goldens, args):
         mpr.check_status(st)
         (mu, lam, c, tr), t_per = _timed(torch, lambda: mpr.find_period(A, 300, traces=True, slots=8, sparse=True,
                                                                         extend=True))
+        # the same search with each power computed while the host reads the previous one's class hash
+        (mup, lamp, cp, trp), t_per_p = _timed(torch, lambda: mpr.find_period(A, 300, traces=True, slots=8,
+                                                                              sparse=True, extend=True,
+                                                                              pipeline=True))
+        pipelined_same = (mup, lamp, cp) == (mu, lam, c) and np.array_equal(trp, tr)
         g, per = goldens[m]
         golden_ok = (mu, lam, c) == per and all(int(tr[k]) == g[k] for k in range(1, 301))
         t0 = time.perf_counter()
@@ -824,7 +833,9 @@ def leg_config3(mpr, torch, goldens, args):
                     "sparse_chain_300_s": round(res["sparse_chain"][1], 4),
                     "chain_equals_square": _same(torch, res["chain"][0], res["square"][0]),
                     "chain_equals_sparse": _same(torch, res["chain"][0], res["sparse_chain"][0]),
-                    "period_search_to_period_s": round(t_per, 4), "gamma_3_300_match_golden": bool(golden_ok),
+                    "period_search_to_period_s": round(t_per, 4),
+                    "period_search_pipelined_s": round(t_per_p, 4), "pipelined_same": bool(pipelined_same),
+                    "gamma_3_300_match_golden": bool(golden_ok),
                     "matches_oracle": bool(oracle_ok),
                     "cpu_baseline": {"value": round(len(rows) * 299 * float(n) * n / t_cpu / 1e9, 3),
                                      "unit": "G pairs/s (dense-equivalent)", "cores": O.threads(),

@@ -71,6 +71,10 @@ typedef enum {
 #define MPR_PERIOD_REUSE_A 4 /* mpr_find_period_ex flag: A's buffer may be
                                 overwritten to hold a power (needs
                                 MPR_PERIOD_SPARSE) */
+#define MPR_PERIOD_PIPELINE 8 /* mpr_find_period_ex flag: compute the next
+                                 power while the host reads the current
+                                 one's class hash (not with
+                                 MPR_PERIOD_REUSE_A) */
 
 /* Arithmetic of a product configuration.  MPR_ARITH_U16: packed uint16
  * saturating add and min.  MPR_ARITH_F16: the operands' f16 images (a
@@ -370,7 +374,16 @@ mpr_status mpr_period_formula(int64_t mu, int64_t lam, int64_t c, const int64_t 
  * *mu_host is then that power's index, the smallest power at which the
  * relation A^(mu+lam) = c (x) A^mu has been checked exactly (at most lam
  * above the least pre-period, which the class hashes place lam below it);
- * lam and c are the least period and its exact offset. */
+ * lam and c are the least period and its exact offset.
+ * MPR_PERIOD_PIPELINE enqueues power k + 1 before the host waits for the
+ * class hash, trace and status of power k (read through pinned host
+ * memory, allocated and freed by the call), so the host round trip of each
+ * power overlaps the next one's work instead of following it (it matters
+ * where a power takes tens of microseconds: small matrices).  Same
+ * results.  The power computed ahead takes a ring buffer, which
+ * mpr_period_workspace_size_ex counts with this flag: a workspace of
+ * `slots` ring powers still confirms periods up to slots - 1.  The call
+ * synchronises the stream before it returns. */
 mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host);
 mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t lda, int64_t kmax, int flags,
                               int64_t *mu_host, int64_t *lam_host, int64_t *c_host, int64_t *traces_host,

@@ -33,6 +33,7 @@ CHAIN_SPARSE = 2
 PERIOD_SPARSE = 1
 PERIOD_EXTEND = 2
 PERIOD_REUSE_A = 4
+PERIOD_PIPELINE = 8
 ARITH_U16 = 0
 ARITH_F16 = 1
 
@@ -454,17 +455,20 @@ def period_workspace_size(n: int, slots: int, flags: int = 0) -> int:
 
 
 def find_period(A, kmax: int, traces: bool = True, slots: int = 64, ws=None, stream=None, sparse: bool = False,
-                extend: bool = False, reuse_a: bool = False):
+                extend: bool = False, reuse_a: bool = False, pipeline: bool = False):
     """(mu, lam, c, traces) with traces[k] = trace of A^k for k = 1..kmax
     (None when traces=False); mu is None when no period is confirmed.
     sparse=True runs the chain steps over the compressed rows of A;
     extend=True stops at the confirming power and fills the later traces
     from the period (exact); reuse_a=True (with sparse) lets the search
-    overwrite A to confirm a period longer than the ring one period late."""
+    overwrite A to confirm a period longer than the ring one period late;
+    pipeline=True computes the next power while the host reads the current
+    one's class hash (same results)."""
     n = A.shape[0]
-    flags = (PERIOD_SPARSE if sparse else 0) | (PERIOD_EXTEND if extend else 0) | (PERIOD_REUSE_A if reuse_a else 0)
+    flags = ((PERIOD_SPARSE if sparse else 0) | (PERIOD_EXTEND if extend else 0) |
+             (PERIOD_REUSE_A if reuse_a else 0) | (PERIOD_PIPELINE if pipeline else 0))
     if ws is None:  # with sparse=True the plan is sized for this A
-        ws = workspace(period_workspace_size(n, slots, flags & PERIOD_REUSE_A) +
+        ws = workspace(period_workspace_size(n, slots, flags & (PERIOD_REUSE_A | PERIOD_PIPELINE)) +
                        (sparse_plan_bytes(A, stream) if sparse else 0), A.device)
     mu, lam, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     tr = np.zeros(kmax + 1, dtype=np.int64) if traces else None

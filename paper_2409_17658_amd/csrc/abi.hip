@@ -259,6 +259,8 @@ static void report_progress(int64_t k, int64_t trace)
     if (fn) fn(k, trace, user);
 }
 
+constexpr int kPeriodFlagsAll = MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND | MPR_PERIOD_REUSE_A | MPR_PERIOD_PIPELINE;
+
 struct PeriodWs {
     uint64_t *row_hash;
     int64_t *hold_R;  // offsets of the power kept in A's buffer (MPR_PERIOD_REUSE_A)
@@ -580,10 +582,12 @@ extern "C" mpr_status mpr_trace_of_product_t(const uint16_t *X, const int64_t *R
 
 extern "C" mpr_status mpr_period_workspace_size_ex(int64_t n, int64_t slots, int flags, size_t *bytes_host)
 {
-    if (n < 0 || slots < 2 || !bytes_host || (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND | MPR_PERIOD_REUSE_A)))
-        return MPR_EINVAL;
+    if (n < 0 || slots < 2 || !bytes_host || (flags & ~kPeriodFlagsAll)) return MPR_EINVAL;
+    if ((flags & MPR_PERIOD_PIPELINE) && (flags & MPR_PERIOD_REUSE_A)) return MPR_EINVAL;
     PeriodWs w = carve_period(nullptr, n, 0, slots, flags);
-    *bytes_host = w.fixed + (size_t)slots * w.slot_bytes;
+    // MPR_PERIOD_PIPELINE: one more buffer, for the power computed ahead
+    const int64_t bufs = slots + ((flags & MPR_PERIOD_PIPELINE) ? 1 : 0);
+    *bytes_host = w.fixed + (size_t)bufs * w.slot_bytes;
     return MPR_OK;
 }
 
@@ -597,9 +601,11 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
                                          void *ws, size_t ws_bytes, mpr_stream stream)
 {
     if (n < 1 || kmax < 1 || !A || !mu_host || !lam_host || !c_host || !ld_ok(lda, n)) return MPR_EINVAL;
-    if (flags & ~(MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND | MPR_PERIOD_REUSE_A)) return MPR_EINVAL;
+    if (flags & ~kPeriodFlagsAll) return MPR_EINVAL;
     const bool sparse = (flags & MPR_PERIOD_SPARSE) != 0;
     const bool reuse_a = (flags & MPR_PERIOD_REUSE_A) != 0;
+    const bool pipeline = (flags & MPR_PERIOD_PIPELINE) != 0;
+    if (pipeline && reuse_a) return MPR_EINVAL;
     // A's buffer can hold a power only once nothing reads A any more (the
     // compressed-K plan replaces it after the first power) and only in the
     // ring's layout (the compare reads both powers with one row stride).
@@ -619,7 +625,7 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
         plan_bytes = sparse_plan_bytes_rows(n, rows);
     }
     PeriodWs w = carve_period(ws, n, ws_bytes, 0, flags, plan_bytes);
-    if (w.slots < 2) return MPR_ENOMEM;
+    if (w.slots < (pipeline ? 3 : 2)) return MPR_ENOMEM;
     int32_t *st = (int32_t *)&w.scal[2];
     if ((r = fill_i32_launch(st, 2, 0, s)) != MPR_OK) return r;
     if ((r = validate_launch(A, n, n, lda, st, s)) != MPR_OK) return r;
@@ -655,6 +661,95 @@ extern "C" mpr_status mpr_find_period_ex(const uint16_t *A, int64_t n, int64_t l
         c = no_rows ? 0 : cmp[1];
         return MPR_OK;
     };
+    if (pipeline) {
+        // Power k + 1 is enqueued before the host waits for the class hash
+        // and trace of power k (copied to pinned memory, each with its
+        // event), so the round trip overlaps a power's work instead of
+        // following it.  Power k + 1 overwrites power k + 1 - M of the ring
+        // of M buffers, so a repeat of power j is confirmed while
+        // k - j < M - 1: the workspace of `slots` holds M = slots + 1.
+        const int64_t M = w.slots;
+        int64_t *pin = nullptr;  // two records of the 8 scalar words
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        auto finish = [&](mpr_status e) {
+            if (hipStreamSynchronize(s) != hipSuccess && e == MPR_OK) e = MPR_EHIP;  // the power computed ahead
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            if (pin) (void)hipHostFree(pin);
+            return e;
+        };
+        if (hipHostMalloc((void **)&pin, 2 * 8 * sizeof(int64_t)) != hipSuccess) return MPR_ENOMEM;
+        if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess)
+            return finish(MPR_EHIP);
+        auto enqueue = [&](int64_t k) -> mpr_status {
+            const int64_t slot = (k - 1) % M;
+            u16 *Nk = slot_N(w, slot);
+            int64_t *Rk = slot_R(w, slot);
+            mpr_status e;
+            if (k == 1) {
+                e = copy_launch(A, lda, Nk, w.ld, n, n, s);
+                if (e == MPR_OK) e = normalise_launch(n, n, Nk, w.ld, nullptr, nullptr, Rk, st, w.row_hash, s);
+            } else {
+                const int64_t ps = (k - 2) % M;
+                e = sparse ? sparse_step_launch(slot_N(w, ps), w.ld, n, w.plan, w.plan_bytes, Nk, w.ld, s)
+                           : gemm_launch(-1, n, n, n, slot_N(w, ps), w.ld, A, lda, Nk, w.ld, s);
+                if (e == MPR_OK)
+                    e = normalise_launch(n, n, Nk, w.ld, slot_R(w, ps), nullptr, Rk, st, w.row_hash, s);
+            }
+            if (e == MPR_OK) e = class_hash_launch(w.row_hash, Rk, n, (uint64_t *)&w.scal[0], s);
+            if (e == MPR_OK) e = trace_launch(Nk, n, w.ld, Rk, &w.scal[1], s);
+            if (e == MPR_OK && (hipMemcpyAsync(pin + 8 * (k & 1), w.scal, 8 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                               s) != hipSuccess ||
+                                hipEventRecord(ev[k & 1], s) != hipSuccess))
+                e = MPR_EHIP;
+            return e;
+        };
+        if ((r = enqueue(1)) != MPR_OK) return finish(r);
+        for (int64_t k = 1; k <= kmax; k++) {
+            if (k + 1 <= kmax && (r = enqueue(k + 1)) != MPR_OK) return finish(r);
+            if (hipEventSynchronize(ev[k & 1]) != hipSuccess) return finish(MPR_EHIP);
+            const volatile int64_t *rec = pin + 8 * (k & 1);
+            const int64_t hash = rec[0], trace = rec[1];
+            const int32_t stv = (int32_t)(rec[2] & 0xFFFFFFFF);
+            if (stv != 0) return finish((mpr_status)stv);
+            if (traces_host) traces_host[k] = trace;
+            report_progress(k, trace);
+            if (!found) {
+                const uint64_t h = (uint64_t)hash;
+                auto range = seen.equal_range(h);
+                for (auto it = range.first; it != range.second && !found; ++it) {
+                    const int64_t j = it->second;
+                    if (k - j >= M - 1) continue;  // power j overwritten (by power k + 1 at the latest)
+                    const int64_t sj = (j - 1) % M, sk = (k - 1) % M;
+                    bool eq = false;
+                    int64_t c = 0;
+                    if ((r = same_class(slot_N(w, sj), slot_R(w, sj), slot_N(w, sk), slot_R(w, sk), eq, c)) != MPR_OK)
+                        return finish(r);
+                    if (eq) {
+                        found = true;
+                        mu = j;
+                        lam = k - j;
+                        cval = c;
+                    }
+                }
+                if (!found) seen.emplace(h, k);
+            }
+            if (found && !traces_host) break;
+            if (found && (flags & MPR_PERIOD_EXTEND)) {
+                for (int64_t j = k + 1; j <= kmax; j++)
+                    traces_host[j] =
+                        traces_host[j - lam] == MPR_ROW_NONE ? MPR_ROW_NONE : traces_host[j - lam] + cval;
+                break;
+            }
+        }
+        if ((r = finish(MPR_OK)) != MPR_OK) return r;
+        if (!found) return MPR_ENOTFOUND;
+        *mu_host = mu;
+        *lam_host = lam;
+        *c_host = cval;
+        return MPR_OK;
+    }
     for (int64_t k = 1; k <= kmax; k++) {
         const int64_t slot = (k - 1) % w.slots;
         u16 *Nk = slot_N(w, slot);

@@ -364,7 +364,7 @@ static inline int32_t info_wide(volatile const int64_t *info, int B)
 
 // Ring powers of a period-mode search: confirms periods up to 7.
 constexpr int kPeriodSlots = 8;
-constexpr int kPeriodFlags = MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND;
+constexpr int kPeriodFlags = MPR_PERIOD_SPARSE | MPR_PERIOD_EXTEND | MPR_PERIOD_PIPELINE;
 
 // Device bytes of a period-mode build of m: A, then the search's workspace
 // (sized with a compressed-K plan for a dense A, since the bytes are

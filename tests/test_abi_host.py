@@ -68,6 +68,9 @@ def test_argument_errors_are_synchronous(mpr):
     assert L.mpr_minplus_power(p, 4, 4, 3, 7, p, 4, p, p, 1 << 20, None, None) == 1
     assert L.mpr_minplus_power(p, 4, 4, 3, 0, p, 4, p, p, 16, None, None) == 2  # workspace too small
     assert L.mpr_build_transfer(12, p, 1 << 20, None) == 1
+    nb = ctypes.c_size_t()
+    assert L.mpr_period_workspace_size_ex(8, 4, 4 | 8, ctypes.byref(nb)) == 1  # pipeline with reuse_a
+    assert L.mpr_period_workspace_size_ex(8, 4, 16, ctypes.byref(nb)) == 1    # no such flag
     # chain_resume: squaring is not a chain, negative steps, in place with another stride
     assert L.mpr_chain_resume(p, 4, 8, p, 8, p, 3, 1, p, 8, p, p, 1 << 20, None, None) == 1
     assert L.mpr_chain_resume(p, 4, 8, p, 8, p, -1, 0, p, 8, p, p, 1 << 20, None, None) == 1

@@ -509,12 +509,14 @@ def test_config1_gamma_m3(mpr):
 
 @pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("extend", [False, True])
-def test_find_period_small_m(mpr, m, extend):
+@pytest.mark.parametrize("pipeline", [False, True])
+def test_find_period_small_m(mpr, m, extend, pipeline):
     """Every trace to k = 60 against the oracle, computed power by power or,
     with extend, computed up to the confirming power and extended by the
-    period after it."""
+    period after it; with pipeline, each power computed while the host reads
+    the previous one's class hash."""
     A = mpr.build_transfer(m)
-    mu, lam, c, tr = mpr.find_period(A, 60, traces=True, extend=extend)
+    mu, lam, c, tr = mpr.find_period(A, 60, traces=True, extend=extend, pipeline=pipeline)
     omu, olam, oc, og = O.find_period(O.transfer(m), 60)
     assert (mu, lam, c) == (omu, olam, oc)
     for k in range(1, 61):
@@ -556,15 +558,41 @@ def test_tiny_and_degenerate_powers_and_periods(mpr):
         mu, lam, c, tr = O.find_period(A, 12)
         for sparse in (False, True):
             for extend in (False, True):
-                got = mpr.find_period(Ad, 12, traces=True, slots=8, sparse=sparse, extend=extend)
-                assert got[:3] == (mu, lam, c), (A.tolist(), got[:3], (mu, lam, c), sparse, extend)
-                assert all(got[3][k] == tr[k] for k in tr), (A.tolist(), sparse, extend)
-                if mu is not None:  # every k <= 12, beyond the oracle's own powers by the period
-                    for k in range(1, 13):
-                        ref = tr[k] if k in tr else tr[mu + (k - mu) % lam]
-                        if k not in tr and ref != O.INF:
-                            ref += c * ((k - mu) // lam)
-                        assert got[3][k] == ref, (A.tolist(), k, sparse, extend)
+                for pipeline in (False, True):
+                    got = mpr.find_period(Ad, 12, traces=True, slots=8, sparse=sparse, extend=extend,
+                                          pipeline=pipeline)
+                    key = (A.tolist(), sparse, extend, pipeline)
+                    assert got[:3] == (mu, lam, c), (key, got[:3], (mu, lam, c))
+                    assert all(got[3][k] == tr[k] for k in tr), key
+                    if mu is not None:  # every k <= 12, beyond the oracle's own powers by the period
+                        for k in range(1, 13):
+                            ref = tr[k] if k in tr else tr[mu + (k - mu) % lam]
+                            if k not in tr and ref != O.INF:
+                                ref += c * ((k - mu) // lam)
+                            assert got[3][k] == ref, (key, k)
+
+
+def test_find_period_pipeline_ring_bound(mpr):
+    """A weighted 5-cycle repeats with period 5 from the first power.  A ring
+    of 6 powers confirms it, computed power by power and with the next power
+    computed ahead (the workspace sized with the pipeline flag holds the
+    extra buffer); a pipelined search given only the 6 buffers of the plain
+    ring confirms periods up to 4 and reports none."""
+    I = O.INF
+    L = 5
+    A = np.full((L, L), I, dtype=np.int64)
+    for i in range(L):
+        A[i, (i + 1) % L] = 1 + (i % 2)
+    mu, lam, c, tr = O.find_period(A, 30)
+    assert lam == L
+    Ad = _dev(mpr, _u16(A))
+    for pipeline in (False, True):
+        got = mpr.find_period(Ad, 30, slots=6, pipeline=pipeline)
+        assert got[:3] == (mu, lam, c), pipeline
+        assert all(got[3][k] == tr[k] for k in tr), pipeline
+    ws = mpr.workspace(mpr.period_workspace_size(L, 6, 0))
+    assert mpr.find_period(Ad, 30, ws=ws, pipeline=True)[0] is None
+    assert mpr.period_workspace_size(L, 6, mpr.PERIOD_PIPELINE) > mpr.period_workspace_size(L, 6, 0)
 
 
 def test_find_period_not_found(mpr):
