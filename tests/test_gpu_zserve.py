@@ -273,6 +273,28 @@ def test_cold_ladder_answers_progressively(serve):
     assert st["early_answers"] >= 3 and st["builds"] == 1
 
 
+def test_small_ladder_not_stuck_behind_large_build(serve):
+    """Ladder builds are scheduled shortest first: an m = 8 ladder (N = 7411,
+    30 products of about 12 ms) started while the m = 9 ladder (30 products
+    of about 0.28 s) is in its giant products is built between them, so an
+    m = 8 query needing its last giant is answered within about a second,
+    long before the m = 9 build ends (alternating products of the two would
+    take about 9 s)."""
+    with serve.Server(baby=32, max_n=1000, max_batch=64, slots=4, hbm_budget_bytes=200 << 30) as S:
+        S.submit(9, 997, 1)
+        time.sleep(2.0)  # m = 9: past its babies, into its giant products
+        S.submit(8, 999, 2)
+        got, t_end = {}, time.monotonic() + 120
+        while len(got) < 2 and time.monotonic() < t_end:
+            for r in S.poll(20):
+                got[r["tag"]] = r
+    big, small = got[1], got[2]
+    assert big["status"] == 0 and big["gamma"] == 4 * 997 + 2
+    assert small["status"] == 0 and small["gamma"] == golden_gamma(8, 999)
+    assert small["t_done"] - small["t_submit"] < 3.0
+    assert small["t_done"] < big["t_done"]
+
+
 def test_server_request_deadline(serve):
     """Requests not launched within request_timeout_s complete with
     MPR_ETIMEDOUT (7): a cold m = 8 query for n = 999 needs the ladder's last
