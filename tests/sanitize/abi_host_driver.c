@@ -36,8 +36,11 @@ int main(void)
     size_t bytes = 0;
     CHECK(mpr_power_workspace_size(1000, 10, MPR_CHAIN_SPARSE, &bytes) == MPR_OK && bytes > 0);
     CHECK(mpr_period_workspace_size_ex(100, 4, MPR_PERIOD_SPARSE, &bytes) == MPR_OK);
-    CHECK(mpr_period_workspace_size_ex(100, 4, 8, &bytes) == MPR_EINVAL);
-    for (int s = 0; s < 8; s++) CHECK(mpr_status_string(s) != NULL);
+    CHECK(mpr_period_workspace_size_ex(100, 4, MPR_PERIOD_PIPELINE, &bytes) == MPR_OK);
+    CHECK(mpr_period_workspace_size_ex(100, 4, MPR_PERIOD_PIPELINE | MPR_PERIOD_REUSE_A, &bytes) == MPR_EINVAL);
+    CHECK(mpr_period_workspace_size_ex(100, 4, 16, &bytes) == MPR_EINVAL);
+    CHECK(mpr_power_workspace_size(300, 10, MPR_CHAIN, &bytes) == MPR_OK && bytes >= 300 * 304 * 2 + 256);
+    for (int s = 0; s < 9; s++) CHECK(mpr_status_string(s) != NULL);
     CHECK(mpr_gemm_config_count() > 0 && mpr_batch_config_count() > 0);
     CHECK(mpr_server_ladder_bytes(9, 32, 1000, 0) > mpr_server_ladder_bytes(9, 32, 1000, 1));
     CHECK(mpr_server_ladder_bytes(9, 32, 1000, 1) > 0 && mpr_server_ladder_bytes(0, 32, 1000, 0) < 0);
