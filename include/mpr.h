@@ -206,7 +206,13 @@ mpr_status mpr_minplus_gemm_norm(int64_t M, int64_t N, int64_t K,
 /* Powers (Algorithm 1, step 3; Algorithm 2, step 3).                  */
 /* ------------------------------------------------------------------ */
 
-/* Workspace bytes for mpr_minplus_power on an n x n matrix. */
+/* Workspace bytes for mpr_minplus_power on an n x n matrix.  For
+ * MPR_CHAIN on a matrix too small to fill the device (fewer than about
+ * two 64 x 64 output tiles per CU) this includes the partial products of
+ * steps whose inner dimension is split into ranges (the minimum over k
+ * taken in parts, then the minimum of the parts: the same bits); a
+ * workspace of only the layout, n * round_up(n, 8) * 2 + 256 bytes, runs
+ * every step unsplit. */
 mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *bytes_host);
 
 /* Canonical form (N_out, R_out) of A^e for the n x n matrix A, e >= 1.

@@ -135,14 +135,22 @@ static size_t gemm_norm_ws(int64_t K, int64_t N, int64_t *ldp_out)
 }
 
 // ------------------------------------------------------------ powers
+// splitk.hip: small products with the inner dimension split.
+int splitk_parts(int64_t M, int64_t N, int64_t K);
+size_t splitk_bytes(int64_t M, int64_t N, int parts);
+mpr_status splitk_launch(int parts, int64_t M, int64_t N, int64_t K, const u16 *A, int64_t lda, const u16 *B,
+                         int64_t ldb, u16 *C, int64_t ldc, u16 *P, hipStream_t s);
+
 struct PowerWs {
     u16 *P, *acc, *Bp, *C;
     int64_t *RP, *Racc, *RC, *s;
     void *plan;         // compressed-K plan of A (MPR_CHAIN_SPARSE)
     size_t plan_bytes;  // its share of the workspace
     bool plan_full;     // sized for the worst case (any A fits)
+    u16 *split;         // MPR_CHAIN: partial products of a split-k step, the rest of the workspace
+    size_t split_bytes;
     int64_t ld;
-    size_t bytes;
+    size_t bytes;       // needed (without the optional partial products)
 };
 
 // Workspace layout of mpr_minplus_power.  The compressed-K plan takes the
@@ -170,7 +178,22 @@ static PowerWs carve_power(void *ws, int64_t n, int schedule, size_t ws_bytes = 
         w.plan = c.take<char>(w.plan_bytes);
     }
     w.bytes = c.used + 256;
+    if (schedule == MPR_CHAIN && ws_bytes > w.bytes + 256) {  // room for the partial products of small steps
+        const size_t at = (size_t)round_up((int64_t)c.used, 256);
+        w.split = ws ? (u16 *)((char *)ws + at) : nullptr;
+        w.split_bytes = ws_bytes - at - 256;
+    }
     return w;
+}
+
+// Workspace that mpr_power_workspace_size reports: the layout plus, for the
+// chain of a small matrix, the partial products of its split-k steps.
+static size_t power_ws_recommended(int64_t n, int schedule)
+{
+    const PowerWs w = carve_power(nullptr, n, schedule);
+    size_t extra = 0;
+    if (schedule == MPR_CHAIN && n > 0) extra = splitk_bytes(n, n, splitk_parts(n, n, n));
+    return w.bytes + (extra ? extra + 256 : 0);
 }
 
 // e - 1 chain steps from a first power: A itself (normalised), or, when N0
@@ -196,10 +219,13 @@ static mpr_status power_chain(const u16 *A, int64_t n, int64_t lda, int64_t e, u
         if (r == MPR_OK) r = normalise_launch(n, n, buf[b], ld[b], nullptr, nullptr, R_out, st, nullptr, s);
     }
     if (r == MPR_OK && sparse && e >= 2) r = sparse_plan_launch(A, n, lda, w.plan, w.plan_bytes, st, s);
+    // a small matrix's steps split k when the workspace holds the partial products
+    int parts = sparse ? 1 : splitk_parts(n, n, n);
+    while (parts > 1 && splitk_bytes(n, n, parts) > w.split_bytes) parts--;
     for (int64_t k = 2; k <= e && r == MPR_OK; k++) {
         const int nb = b ^ 1;
         r = sparse ? sparse_step_launch(buf[b], ld[b], n, w.plan, w.plan_bytes, buf[nb], ld[nb], s)
-                   : gemm_launch(-1, n, n, n, buf[b], ld[b], A, lda, buf[nb], ld[nb], s);
+                   : splitk_launch(parts, n, n, n, buf[b], ld[b], A, lda, buf[nb], ld[nb], w.split, s);
         if (r == MPR_OK) r = normalise_launch(n, n, buf[nb], ld[nb], R_out, nullptr, R_out, st, nullptr, s);
         b = nb;
     }
@@ -465,7 +491,7 @@ extern "C" mpr_status mpr_minplus_gemm_norm(int64_t M, int64_t N, int64_t K, con
 extern "C" mpr_status mpr_power_workspace_size(int64_t n, int64_t e, int schedule, size_t *bytes_host)
 {
     if (n < 0 || e < 1 || !bytes_host || schedule < MPR_CHAIN || schedule > MPR_CHAIN_SPARSE) return MPR_EINVAL;
-    *bytes_host = carve_power(nullptr, n, schedule).bytes;
+    *bytes_host = power_ws_recommended(n, schedule);
     return MPR_OK;
 }
 

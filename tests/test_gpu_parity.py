@@ -317,6 +317,31 @@ def test_power_random_and_banded(mpr, schedule):
         assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
 
 
+@pytest.mark.parametrize("arith", ["u16", "f16"])
+def test_power_split_k_steps(mpr, arith):
+    """Chains of matrices too small to fill the device split each step's k
+    into ranges (a minimum over k taken in parts, then the minimum of the
+    parts): n = 300 (2 ranges, the last 140 deep), 520 and 848 (several
+    ranges, ragged tails), 200 (k too short to split).  Every power equals
+    the oracle's chain, and equals the unsplit chain that a workspace of
+    only the layout's size gives."""
+    prev = mpr.get_arith()
+    mpr.set_arith(arith)
+    try:
+        for n, e, seed in [(300, 6, 21), (520, 5, 22), (848, 4, 23), (200, 5, 24)]:
+            print("split-k", arith, n, e, flush=True)
+            X = synth.random_matrix(n, n, seed, 0, 40, 0.35)
+            A = _dev(mpr, X)
+            N, R = mpr.minplus_power(A, e, 0)
+            Nr, Rr = O.power_chain(O.from_u16(X), e)
+            assert np.array_equal(_host(N), _u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr)
+            ld = (n + 7) // 8 * 8
+            N1, R1 = mpr.minplus_power(A, e, 0, ws=mpr.workspace(n * ld * 2 + 256))
+            assert torch.equal(N1, N) and torch.equal(R1, R)
+    finally:
+        mpr.set_arith(prev)
+
+
 def test_power_empty_rows_stay_empty(mpr):
     X = synth.random_matrix(90, 90, 12, 0, 9, 0.2)
     X[3, :] = 0xFFFF
