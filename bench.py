@@ -1075,6 +1075,8 @@ def main():
     ap.add_argument("--m10-kmax", type=int, default=35)
     ap.add_argument("--with-m9", type=int, default=1, help="config3: also the m = 9 run")
     ap.add_argument("--m10-sparse", type=int, default=1)
+    ap.add_argument("--sparse-form", default="auto", choices=["auto", "tiles", "entries"],
+                    help="form of the compressed-K chain steps (library default: auto)")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--f16-form", type=int, default=1, help="also time the step in the f16 form (labelled)")
     ap.add_argument("--slow-reps", type=int, default=3)
@@ -1113,6 +1115,7 @@ def main():
 
     torch.cuda.set_device(0)
     mpr.init(0)
+    mpr.set_sparse_form(args.sparse_form)
     if args.copy_calibration:
         copy_calibration(torch)
     if args.workload == "gemm":

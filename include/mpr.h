@@ -452,6 +452,19 @@ mpr_status mpr_batch_power(const mpr_chain_desc *descs_host, int count,
  * bit.  Process-wide setting. */
 mpr_status mpr_set_sparse_arith(int arith);
 
+/* Form of the compressed-K chain steps (Algorithm 2's step restricted to
+ * the rows L_J of A that reach each block J of 64 output columns):
+ * MPR_SPARSE_TILES multiplies N[:, L_J] by the dense rows A[L_J, J];
+ * MPR_SPARSE_ENTRIES (uint16 arithmetic only; the f16 form always takes
+ * the tiles) visits only the finite entries of A[L_J, J], one output
+ * column per wave; MPR_SPARSE_AUTO (the default) picks by the matrix's
+ * size.  Both give the same powers bit for bit.  MPR_EINVAL for other
+ * values.  Process-wide setting. */
+#define MPR_SPARSE_AUTO 0
+#define MPR_SPARSE_TILES 1
+#define MPR_SPARSE_ENTRIES 2
+mpr_status mpr_set_sparse_form(int form);
+
 /* Process-wide arithmetic (MPR_ARITH_U16, the default, or MPR_ARITH_F16) of
  * every product whose configuration the library picks: products with
  * cfg = -1 (the tile table of that arithmetic), the steps of

@@ -115,6 +115,7 @@ _SIGS = {
     "mpr_batch_config_count": (_I, []),
     "mpr_batch_config_info": (_I, [_I, _P, _P, _P]),
     "mpr_set_sparse_arith": (_I, [_I]),
+    "mpr_set_sparse_form": (_I, [_I]),
     "mpr_set_arith": (_I, [_I]),
     "mpr_get_arith": (_I, []),
     "mpr_set_batch_weights": (_I, [_P, _I]),
@@ -588,6 +589,17 @@ def _arith_code(arith: str) -> int:
 def set_sparse_arith(arith: str):
     """'u16' (default) or 'f16' for the compressed-K chain steps."""
     _ok(lib().mpr_set_sparse_arith(_arith_code(arith)), "mpr_set_sparse_arith")
+
+
+SPARSE_FORMS = {"auto": 0, "tiles": 1, "entries": 2}
+
+
+def set_sparse_form(form: str):
+    """'auto' (default), 'tiles' or 'entries': the form of the compressed-K
+    chain steps (entries: only the finite entries of A, uint16 only)."""
+    if form not in SPARSE_FORMS:
+        raise ValueError("sparse form is 'auto', 'tiles' or 'entries'")
+    _ok(lib().mpr_set_sparse_form(SPARSE_FORMS[form]), "mpr_set_sparse_form")
 
 
 def set_arith(arith: str):

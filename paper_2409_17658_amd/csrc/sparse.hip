@@ -21,6 +21,9 @@ namespace mpr {
 using SCfg = TileCfg<64, 64, 32, 4, 8>;  // 128 threads; 64-column blocks
 constexpr int SBN = SCfg::BN;
 constexpr int SBK = SCfg::BK;
+// The entry-list form from this size on (m >= 8 transfer matrices); below
+// it the tile form is faster (too few 512-row tiles to fill the device).
+constexpr int64_t kEntryFormMinN = 7000;
 
 // Does row l of A have a finite entry in columns [j0, j0 + SBN)?
 __device__ __forceinline__ bool row_hits_block(const u16 *A, int64_t lda, int64_t l, int64_t j0, int64_t n, bool vec)
@@ -233,6 +236,214 @@ __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) v
     tile_store<SCfg>(C, ldc, n, n, m0, n0, vec != 0, acc);
 }
 
+// ------------------------------------------- entry-list form of the step
+// The tile above multiplies whole 64-column rows of A[L_J, J]; for a
+// transfer matrix about nine in ten of those entries are infinite (a
+// column has 25 to 120 finite entries, its block's L_J ten times as many),
+// so nine in ten of its pairs cannot win.  This form visits the finite
+// entries only.  A block takes 512 rows and one column block; each of its
+// eight waves owns 8 whole columns (all 512 rows, 8 per lane), so the
+// entries of a column are the same for every lane of the wave.  Per slice
+// of 32 rows of L_J, the gathered N[rows, L_J-slice] is stored in LDS
+// transposed (l-major), and per column a wave holds the column's 32 values
+// of A (one per lane, loaded a slice ahead straight into registers), turns
+// the finite ones into a wave-uniform bit mask, and for each set bit l adds
+// the scalar A[l][j] to the lane's eight values N[i][l] (one 16-byte LDS
+// read) and keeps the minimum.  Two columns are walked together, two reads
+// in flight; a column whose mask has run out adds infinity, which changes
+// nothing, and a column with many entries in the slice walks all 32 rows
+// (one read for both columns, infinity where A has no entry).  The same
+// plan, the same minimum over the same entries: the same bits as the tile
+// form.
+typedef const __attribute__((address_space(1))) unsigned char gbytes;
+constexpr int EBM = 512;                 // rows per block
+constexpr int ENT = 512;                 // threads: 8 waves
+constexpr int ECOLS = SBN / (ENT / 64);  // columns per wave
+constexpr int ERL = EBM / 64;            // rows per lane
+constexpr int ELDN = EBM + 8;            // transposed slice row (u16), 16-byte aligned
+constexpr int E_NT = SBK * ELDN;         // one transposed slice buffer
+constexpr int ERP = ENT / SBK;           // row pairs staged per slice by one k
+static_assert(ENT == EBM, "one output row per thread in the epilogue");
+static_assert(EBM % (2 * ERP) == 0, "staging covers the tile's rows");
+static_assert(ECOLS == 8 && ERL == 8, "a lane: 8 columns of A (one 16-byte load), 8 rows (one 16-byte read)");
+static_assert(SBN * ELDN <= 2 * E_NT, "the output tile fits the two slice buffers");
+constexpr int kEntryDense = 8;           // more entries than this in a column's slice: walk all 32 rows
+constexpr int ESV = EBM / ERP;           // values a thread stages per slice
+
+// One 512-row tile of the entry-list step; FULL: every row of the tile is
+// < n (so the gathers need no row test).
+template <bool FULL>
+__device__ __forceinline__ void entry_tile(const u16 *__restrict__ Np, int64_t ldn, int64_t n, int64_t m0,
+                                           int64_t j0, const int32_t *__restrict__ idx, const u16 *__restrict__ Bp,
+                                           int64_t kbeg, int64_t nk, u16 *__restrict__ C, int64_t ldc, int vec,
+                                           u16 *nt)
+{
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    u16x2 acc[ECOLS][ERL / 2];
+#pragma unroll
+    for (int c = 0; c < ECOLS; c++)
+#pragma unroll
+        for (int h = 0; h < ERL / 2; h++) acc[c][h] = (u16x2){0xFFFF, 0xFFFF};
+
+    // staging: thread (k = t % 32, row pair p = t / 32) gathers
+    // N[m0 + 2 ERP e + 2p + h][L_J[k]], h < 2.  The values stay as loaded
+    // until they are stored (the wait for them falls after the slice's
+    // compute), and the column index is read one slice ahead.
+    const int sk = (int)(threadIdx.x % SBK), sp = (int)(threadIdx.x / SBK);  // sk == lane % 32
+    const gu16 *gN = glob(Np);
+    const gbytes *gNb = (const gbytes *)(gN + m0 * ldn);  // this tile's rows; offsets < 2^32 (host)
+    const uint32_t rowb = (uint32_t)ldn * 2u;             // bytes per row
+    const int nloc = (int)(n - m0 < EBM ? n - m0 : EBM);  // rows of the tile below n (>= 1)
+    const __attribute__((address_space(1))) int32_t *gi = glob(idx) + kbeg;
+    const gu16 *gB = glob(Bp) + kbeg * SBN;
+    uint32_t sv[ESV];
+    uint4 bn, bcur;  // A[L_J[32 sl + lane % 32]][j0 + 8 w .. + 7]: the next slice's, this one's
+    auto row_of = [&](int e) { return (e >> 1) * (2 * ERP) + 2 * sp + (e & 1); };
+    auto load = [&](int64_t sl, uint32_t col) {
+        bn = gload16(gB + (sl * SBK + sk) * SBN + w * ECOLS);
+        if (FULL) {
+            const uint32_t o = (uint32_t)(2 * sp) * rowb + col * 2u;
+#pragma unroll
+            for (int e = 0; e < ESV; e++)
+                sv[e] = *(const gu16 *)(gNb + (uint32_t)(o + (uint32_t)((e >> 1) * (2 * ERP) + (e & 1)) * rowb));
+        } else {
+            // rows past n read the last row (every load unconditional, so
+            // none waits for another); store() puts infinity in their place
+#pragma unroll
+            for (int e = 0; e < ESV; e++) {
+                const int r = row_of(e);
+                const uint32_t rr = (uint32_t)(r < nloc ? r : nloc - 1);
+                sv[e] = *(const gu16 *)(gNb + (uint32_t)(rr * rowb + col * 2u));
+            }
+        }
+    };
+    auto store = [&](int buf) {
+        u16 *q = nt + buf * E_NT + sk * ELDN + 2 * sp;
+#pragma unroll
+        for (int e = 0; e < ESV / 2; e++) {
+            uint32_t lo = sv[2 * e], hi = sv[2 * e + 1];
+            if (!FULL) {
+                lo = row_of(2 * e) < nloc ? lo : 0xFFFFu;
+                hi = row_of(2 * e + 1) < nloc ? hi : 0xFFFFu;
+            }
+            *(uint32_t *)(q + 2 * ERP * e) = lo | (hi << 16);
+        }
+    };
+    auto upd = [&](int c, const uint4 &v, uint32_t wgt) {
+        const u16x2 a = (u16x2){(u16)wgt, (u16)wgt};
+        const u16x2 s0 = add_sat(as_u16x2(v.x), a), s1 = add_sat(as_u16x2(v.y), a);
+        const u16x2 s2 = add_sat(as_u16x2(v.z), a), s3 = add_sat(as_u16x2(v.w), a);
+        acc[c][0] = min2(acc[c][0], s0);
+        acc[c][1] = min2(acc[c][1], s1);
+        acc[c][2] = min2(acc[c][2], s2);
+        acc[c][3] = min2(acc[c][3], s3);
+    };
+    auto compute = [&](int buf) {
+        const u16 *nl = nt + buf * E_NT + lane * ERL;
+        // lanes 0-31: column c, lanes 32-63: column c + 1, k = lane % 32
+        const int hsh = (lane >> 5) * 16;
+#pragma unroll
+        for (int c = 0; c < ECOLS; c += 2) {
+            const uint32_t bv = (comp(bcur, c / 2) >> hsh) & 0xFFFFu;
+            const uint64_t mask = __ballot(bv != 0xFFFFu);
+            uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+            if (__builtin_popcount(lo) > kEntryDense || __builtin_popcount(hi) > kEntryDense) {
+#pragma unroll
+                for (int k = 0; k < SBK; k++) {
+                    const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)bv, k);
+                    const uint32_t wh = (uint32_t)__builtin_amdgcn_readlane((int)bv, k + 32);
+                    const uint4 v = *(const uint4 *)(nl + k * ELDN);
+                    upd(c, v, wl);
+                    upd(c + 1, v, wh);
+                }
+                continue;
+            }
+            while (lo | hi) {
+                // an exhausted mask reads row 31 and adds infinity (no branch)
+                const int kl = __builtin_ctz(lo | 0x80000000u), kh = __builtin_ctz(hi | 0x80000000u);
+                const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)bv, kl);
+                const uint32_t rh = (uint32_t)__builtin_amdgcn_readlane((int)bv, kh + 32);
+                const uint32_t wl = lo ? rl : 0xFFFFu, wh = hi ? rh : 0xFFFFu;
+                lo &= lo - 1u;
+                hi &= hi - 1u;
+                const uint4 vl = *(const uint4 *)(nl + kl * ELDN);
+                const uint4 vh = *(const uint4 *)(nl + kh * ELDN);
+                upd(c, vl, wl);
+                upd(c + 1, vh, wh);
+            }
+        }
+    };
+    if (nk > 0) {
+        uint32_t col = (uint32_t)gi[sk];
+        load(0, col);
+        col = nk > 1 ? (uint32_t)gi[SBK + sk] : 0u;
+        store(0);
+        bcur = bn;
+        __syncthreads();
+        for (int64_t sl = 0; sl < nk; sl++) {
+            const int buf = (int)(sl & 1);
+            if (sl + 1 < nk) {
+                load(sl + 1, col);
+                col = sl + 2 < nk ? (uint32_t)gi[(sl + 2) * SBK + sk] : 0u;
+            }
+            compute(buf);
+            if (sl + 1 < nk) {
+                store(buf ^ 1);
+                bcur = bn;
+            }
+            __syncthreads();
+        }
+    }
+    // epilogue: the tile through LDS as [column][row], then each thread
+    // writes one row's 64 columns in 16-byte pieces
+    u16 *ct = nt;
+#pragma unroll
+    for (int c = 0; c < ECOLS; c++)
+        *(uint4 *)(ct + (w * ECOLS + c) * ELDN + lane * ERL) =
+            make_uint4(as_u32(acc[c][0]), as_u32(acc[c][1]), as_u32(acc[c][2]), as_u32(acc[c][3]));
+    __syncthreads();
+    const int r = (int)threadIdx.x;
+    const int64_t i = m0 + r;
+    if (i >= n) return;
+    gu16 *crow = glob(C) + i * ldc + j0;
+#pragma unroll
+    for (int c8 = 0; c8 < SBN; c8 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = ct[(c8 + q) * ELDN + r];
+        if (vec && j0 + c8 + 8 <= n) {
+            gstore16(crow + c8, make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
+                                           v[6] | (v[7] << 16)));
+        } else {
+            for (int q = 0; q < 8; q++)
+                if (j0 + c8 + q < n) crow[c8 + q] = (u16)v[q];
+        }
+    }
+}
+
+__global__ __launch_bounds__(ENT) __attribute__((amdgpu_waves_per_eu(4))) void sp_entry_kernel(
+    const u16 *__restrict__ Np, int64_t ldn, int64_t n, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ order, const int32_t *__restrict__ idx, const u16 *__restrict__ Bp,
+    u16 *__restrict__ C, int64_t ldc, int tiles_m, int nblk, int64_t cap, int vec)
+{
+    __shared__ __attribute__((aligned(16))) u16 nt[2 * E_NT];
+    const int t = (int)blockIdx.x;
+    if (t >= tiles_m * nblk) return;
+    // Column blocks costliest first, all row tiles of one column block
+    // consecutively (one strip of rows at a time, blocks costliest first
+    // within it, measured slower: the last strip's costly blocks start late).
+    const int tm = t % tiles_m, J = order[t / tiles_m];
+    const int64_t m0 = (int64_t)tm * EBM, j0 = (int64_t)J * SBN;
+    // A plan that did not fit its workspace (sp_fill_kernel reported it and
+    // wrote nothing) leaves the tile infinite, as the tile form does.
+    const int64_t kbeg = off[J];
+    const int64_t nk = off[nblk] > cap ? 0 : (off[J + 1] - kbeg) / SBK;
+    if (m0 + EBM <= n)
+        entry_tile<true>(Np, ldn, n, m0, j0, idx, Bp, kbeg, nk, C, ldc, vec, nt);
+    else
+        entry_tile<false>(Np, ldn, n, m0, j0, idx, Bp, kbeg, nk, C, ldc, vec, nt);
+}
+
 // ------------------------------------------------------------ host side
 // Plan layout: counts[nblk + 1] | off[nblk + 1] | order[nblk] | idx[cap] |
 // Bp[cap * SBN], every piece 256-byte aligned; cap (rows) follows from the
@@ -327,15 +538,35 @@ mpr_status sparse_plan_launch(const u16 *A, int64_t n, int64_t lda, void *ws, si
 }
 
 static std::atomic<int> g_sparse_arith{MPR_ARITH_U16};  // process-wide, set from any thread
+static std::atomic<int> g_sparse_form{MPR_SPARSE_AUTO};
+
+// The form a step of an n x n matrix takes: the entry-list form in uint16
+// once it has enough blocks to fill the device, else the tile form.
+static bool use_entry_form(int64_t n)
+{
+    if (g_sparse_arith == MPR_ARITH_F16) return false;
+    const int form = g_sparse_form;
+    if (form != MPR_SPARSE_AUTO) return form == MPR_SPARSE_ENTRIES;
+    return n >= kEntryFormMinN;
+}
 
 mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, size_t bytes, u16 *C, int64_t ldc,
                               hipStream_t s)
 {
     SparsePlan p = carve_plan(ws, n, bytes);
+    const int vec = aligned16(C) && ldc % 8 == 0;
+    if (use_entry_form(n) && (int64_t)EBM * ldn * 2 < ((int64_t)1 << 32)) {
+        const int64_t tiles_m = (n + EBM - 1) / EBM;
+        const int64_t tiles = tiles_m * p.nblk;
+        if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
+        hipLaunchKernelGGL(sp_entry_kernel, dim3((unsigned)tiles), dim3(ENT), 0, s, Np, ldn, n,
+                           (const int64_t *)p.off, (const int32_t *)p.order, (const int32_t *)p.idx,
+                           (const u16 *)p.Bp, C, ldc, (int)tiles_m, (int)p.nblk, p.cap, vec);
+        return check_launch();
+    }
     const int64_t tiles_m = (n + SCfg::BM - 1) / SCfg::BM;
     const int64_t tiles = tiles_m * p.nblk;
     if (tiles > (int64_t)INT32_MAX - 8) return MPR_EUNSUPPORTED;
-    const int vec = aligned16(C) && ldc % 8 == 0;
     auto kernel = g_sparse_arith == MPR_ARITH_F16 ? sp_step_kernel<true> : sp_step_kernel<false>;
     hipLaunchKernelGGL(kernel, dim3((unsigned)tiles), dim3(SCfg::NT), 0, s, Np, ldn, n, (const int64_t *)p.off,
                        (const int32_t *)p.order, (const int32_t *)p.idx, (const u16 *)p.Bp, C, ldc, (int)tiles_m,
@@ -344,6 +575,13 @@ mpr_status sparse_step_launch(const u16 *Np, int64_t ldn, int64_t n, void *ws, s
 }
 
 }  // namespace mpr
+
+extern "C" mpr_status mpr_set_sparse_form(int form)
+{
+    if (form != MPR_SPARSE_AUTO && form != MPR_SPARSE_TILES && form != MPR_SPARSE_ENTRIES) return MPR_EINVAL;
+    mpr::g_sparse_form = form;
+    return MPR_OK;
+}
 
 extern "C" mpr_status mpr_set_sparse_arith(int arith)
 {

@@ -119,6 +119,17 @@ def test_configs_describe_themselves(mpr):
         autotune.load_table()
 
 
+def test_sparse_form_setting(mpr):
+    """The form of the compressed-K step is a process-wide setting with three
+    values; anything else is refused by the binding and by the library."""
+    for f in ("tiles", "entries", "auto"):
+        mpr.set_sparse_form(f)
+    with pytest.raises(ValueError):
+        mpr.set_sparse_form("dense")
+    assert mpr.lib().mpr_set_sparse_form(3) == 1 and mpr.lib().mpr_set_sparse_form(-1) == 1  # MPR_EINVAL
+    assert mpr.lib().mpr_set_sparse_form(0) == 0
+
+
 def test_batch_weights_install_and_reset(mpr):
     """Weights of the batched-configuration model: one per configuration,
     non-negative, each arithmetic keeping one; None restores the prior."""

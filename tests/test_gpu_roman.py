@@ -84,15 +84,23 @@ def test_border_m4_period_and_loss(mpr, paper_values):
         assert tr[n] - n * shift == (12 if n == 11 else n), n
 
 
+@pytest.mark.parametrize("form", ["tiles", "entries"])
 @pytest.mark.parametrize("m", [1, 3, 5, 6, 7, 8])
-def test_sparse_chain_digests(mpr, m):
+def test_sparse_chain_digests(mpr, m, form):
     """The compressed-K chain (only rows of A reaching each column block)
-    gives the same canonical powers, bit for bit, as the oracle goldens."""
+    gives the same canonical powers, bit for bit, as the oracle goldens, in
+    both forms of its step (dense rows of A per block, or A's finite
+    entries only)."""
+    print("sparse chain", m, form, flush=True)
     g = load(m)
     A = mpr.build_transfer(m)
-    for k in (1, 2, 3, 26, 64, 300):
-        N, R = mpr.minplus_power(A, k, mpr.CHAIN_SPARSE)
-        assert digest(N, R) == g["digest_sha256"][str(k)], k
+    mpr.set_sparse_form(form)
+    try:
+        for k in (1, 2, 3, 26, 64, 300):
+            N, R = mpr.minplus_power(A, k, mpr.CHAIN_SPARSE)
+            assert digest(N, R) == g["digest_sha256"][str(k)], k
+    finally:
+        mpr.set_sparse_form("auto")
 
 
 def test_sparse_period_matches(mpr):
@@ -104,18 +112,23 @@ def test_sparse_period_matches(mpr):
         assert all(tr[k] == g["trace"][str(k)] for k in range(1, 301))
 
 
-@pytest.mark.parametrize("arith", ["f16", "u16"])
-def test_sparse_chain_random_and_edge_blocks(mpr, arith):
-    """Both arithmetic forms of the compressed-K step; the last two cases
-    have entries large enough that the f16 form recomputes blocks (their
-    normalised powers stay <= 0x7FFF, so no step overflows)."""
+@pytest.mark.parametrize("arith,form", [("f16", "tiles"), ("u16", "tiles"), ("u16", "entries")])
+def test_sparse_chain_random_and_edge_blocks(mpr, arith, form):
+    """Both arithmetic forms of the compressed-K step and both forms of the
+    uint16 step (dense rows of A per block, or its finite entries only);
+    the cases with entries up to 3000 and 0x3FFF are large enough that the
+    f16 form recomputes blocks (their normalised powers stay <= 0x7FFF, so
+    no step overflows).  Sizes cover partial row blocks of 256 and of 64, a
+    single short block, and a nearly dense last case."""
     import oracle as O
     import synth
 
     mpr.set_sparse_arith(arith)
+    mpr.set_sparse_form(form)
     try:
         for n, frac, e, hi in [(700, 0.95, 6, 40), (333, 0.99, 9, 40), (129, 0.5, 5, 40), (64, 0.9, 4, 40),
-                               (300, 0.9, 4, 3000), (200, 0.97, 2, 0x3FFF)]:
+                               (300, 0.9, 4, 3000), (200, 0.97, 2, 0x3FFF), (37, 0.8, 3, 40), (530, 0.1, 3, 60)]:
+            print("sparse random", arith, form, n, flush=True)
             X = synth.random_matrix(n, n, 77 + n, 0, hi, frac)
             X[:, 64:128] = 0xFFFF  # an empty column block
             N, R = mpr.minplus_power(mpr.to_device(X), e, mpr.CHAIN_SPARSE)
@@ -123,6 +136,7 @@ def test_sparse_chain_random_and_edge_blocks(mpr, arith):
             assert np.array_equal(N.cpu().numpy(), O.to_u16(Nr)) and np.array_equal(R.cpu().numpy(), Rr), n
     finally:
         mpr.set_sparse_arith("u16")
+        mpr.set_sparse_form("auto")
 
 
 def test_sparse_chain_u16_digests(mpr):
