@@ -267,7 +267,7 @@ static_assert(ENT == EBM, "one output row per thread in the epilogue");
 static_assert(EBM % (2 * ERP) == 0, "staging covers the tile's rows");
 static_assert(ECOLS == 8 && ERL == 8, "a lane: 8 columns of A (one 16-byte load), 8 rows (one 16-byte read)");
 static_assert(SBN * ELDN <= 2 * E_NT, "the output tile fits the two slice buffers");
-constexpr int kEntryDense = 8;           // more entries than this in a column's slice: walk all 32 rows
+constexpr int kEntryDense = 16;          // more entries than this in a column's slice: walk all 32 rows
 constexpr int ESV = EBM / ERP;           // values a thread stages per slice
 
 // One 512-row tile of the entry-list step; FULL: every row of the tile is
@@ -359,13 +359,14 @@ __device__ __forceinline__ void entry_tile(const u16 *__restrict__ Np, int64_t l
                 continue;
             }
             while (lo | hi) {
-                // an exhausted mask reads row 31 and adds infinity (no branch)
+                // an exhausted mask reads row 31 and adds infinity (no branch;
+                // the test is on the scanned bit, so it stays scalar)
                 const int kl = __builtin_ctz(lo | 0x80000000u), kh = __builtin_ctz(hi | 0x80000000u);
                 const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)bv, kl);
                 const uint32_t rh = (uint32_t)__builtin_amdgcn_readlane((int)bv, kh + 32);
-                const uint32_t wl = lo ? rl : 0xFFFFu, wh = hi ? rh : 0xFFFFu;
-                lo &= lo - 1u;
-                hi &= hi - 1u;
+                const uint32_t wl = (lo >> kl) & 1u ? rl : 0xFFFFu, wh = (hi >> kh) & 1u ? rh : 0xFFFFu;
+                lo &= ~(1u << kl);
+                hi &= ~(1u << kh);
                 const uint4 vl = *(const uint4 *)(nl + kl * ELDN);
                 const uint4 vh = *(const uint4 *)(nl + kh * ELDN);
                 upd(c, vl, wl);
