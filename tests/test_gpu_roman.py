@@ -178,17 +178,24 @@ def test_sparse_plan_sized_for_the_matrix(mpr):
     assert e.value.status == 1  # no status word: refused before any launch
 
 
+@pytest.mark.parametrize("form", ["auto", "entries"])
 @pytest.mark.parametrize("m", [4, 6, 7])
-def test_period_with_a_reused_buffer(mpr, m):
+def test_period_with_a_reused_buffer(mpr, m, form):
     """A ring of two powers plus A's own buffer (for matrices too large for
     a longer ring): a period the ring can not confirm (lam >= 2) is
     confirmed exactly one period after the class repeat, so mu comes out
     lam above the least pre-period; lam, c and every trace equal the
-    goldens (m = 4 has lam = 1, confirmed in the ring)."""
+    goldens (m = 4 has lam = 1, confirmed in the ring).  Both forms of the
+    compressed-K step (these sizes take the tile form by default)."""
+    print("reuse_a", m, form, flush=True)
     g = load(m)
     mu0, lam0, c0 = g["period"]
     A = mpr.build_transfer(m)
-    mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=2, sparse=True, extend=True, reuse_a=True)
+    mpr.set_sparse_form(form)
+    try:
+        mu, lam, c, tr = mpr.find_period(A, 300, traces=True, slots=2, sparse=True, extend=True, reuse_a=True)
+    finally:
+        mpr.set_sparse_form("auto")
     assert (mu, lam, c) == ((mu0 if lam0 < 2 else mu0 + lam0), lam0, c0)
     for k in range(1, 301):
         assert tr[k] == g["trace"][str(k)], k
