@@ -92,6 +92,21 @@ def test_workspace_sizes(mpr):
         mpr.period_workspace_size(100, 1)
 
 
+def test_chain_workspace_holds_split_k_parts(mpr):
+    """The chain of a matrix too small to fill the device with 64 x 64 tiles
+    gets room for the partial products of split-k steps (each range of k
+    at least 128 deep, at most 8 ranges); a large one gets the layout only
+    (its ping-pong buffer plus 256 bytes).  Sizes as on a 256-CU device."""
+    layout = lambda n: n * ((n + 7) // 8 * 8) * 2 + 256
+    assert mpr.power_workspace_size(8192, 5, mpr.CHAIN) == layout(8192)
+    assert mpr.power_workspace_size(2000, 5, mpr.CHAIN) == layout(2000)  # 1024 tiles
+    assert mpr.power_workspace_size(200, 5, mpr.CHAIN) == layout(200)  # k = 200 is too short to split
+    # n = 300: 25 tiles, k = 300 gives 2 ranges, so one partial product
+    assert mpr.power_workspace_size(300, 5, mpr.CHAIN) == layout(300) + 300 * 304 * 2 + 256
+    # n = 848: 196 tiles, 6 ranges of k (ceil(1024 / 196) = 6 <= 848 // 128)
+    assert mpr.power_workspace_size(848, 5, mpr.CHAIN) == layout(848) + 5 * 848 * 848 * 2 + 256
+
+
 def test_configs_describe_themselves(mpr):
     for c in range(mpr.gemm_config_count()):
         info = mpr.gemm_config_info(c)
