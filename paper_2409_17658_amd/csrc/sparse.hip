@@ -251,8 +251,9 @@ __global__ __launch_bounds__(SCfg::NT) __attribute__((amdgpu_waves_per_eu(4))) v
 // the scalar A[l][j] to the lane's eight values N[i][l] (one 16-byte LDS
 // read) and keeps the minimum.  Two columns are walked together, two reads
 // in flight; a column whose mask has run out adds infinity, which changes
-// nothing, and a column with many entries in the slice walks all 32 rows
-// (one read for both columns, infinity where A has no entry).  The same
+// nothing, and a pair with many entries in the slice walks its rows in
+// order (one read for both columns, infinity where one of them has no
+// entry, rows where neither has one skipped).  The same
 // plan, the same minimum over the same entries: the same bits as the tile
 // form.
 typedef const __attribute__((address_space(1))) unsigned char gbytes;
@@ -267,7 +268,7 @@ static_assert(ENT == EBM, "one output row per thread in the epilogue");
 static_assert(EBM % (2 * ERP) == 0, "staging covers the tile's rows");
 static_assert(ECOLS == 8 && ERL == 8, "a lane: 8 columns of A (one 16-byte load), 8 rows (one 16-byte read)");
 static_assert(SBN * ELDN <= 2 * E_NT, "the output tile fits the two slice buffers");
-constexpr int kEntryDense = 16;          // more entries than this in a column's slice: walk all 32 rows
+constexpr int kEntryDense = 12;          // more entries than this in a column's slice: walk the rows in order
 constexpr int ESV = EBM / ERP;           // values a thread stages per slice
 
 // One 512-row tile of the entry-list step; FULL: every row of the tile is
@@ -348,8 +349,10 @@ __device__ __forceinline__ void entry_tile(const u16 *__restrict__ Np, int64_t l
             const uint64_t mask = __ballot(bv != 0xFFFFu);
             uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
             if (__builtin_popcount(lo) > kEntryDense || __builtin_popcount(hi) > kEntryDense) {
+                const uint32_t any = lo | hi;  // rows where neither column has an entry are skipped
 #pragma unroll
                 for (int k = 0; k < SBK; k++) {
+                    if (!((any >> k) & 1u)) continue;
                     const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)bv, k);
                     const uint32_t wh = (uint32_t)__builtin_amdgcn_readlane((int)bv, k + 32);
                     const uint4 v = *(const uint4 *)(nl + k * ELDN);
